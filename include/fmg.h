@@ -1,0 +1,135 @@
+/*
+ * fmg.h -- C interface of the MI355X (gfx950) solver for the 3D Poisson
+ * equation L u = f, u = 0 on the boundary of the unit cube, by cell-centered
+ * FAS full multigrid with optional segmental refinement.
+ *
+ * Method: Adams, Brown, Knepley, Samtaney, "Segmental Refinement: A Multigrid
+ * Technique for Data Locality" (arXiv:1406.7808):
+ *   - problem and cell-centered grid: Sec. 2, Eqs. (1)-(2);
+ *   - FAS V-cycle: Sec. 3.1, Eqs. (3)-(4), Fig. 1;
+ *   - full multigrid F(alpha, nu1, nu2): Sec. 3.2, Fig. 2;
+ *   - segmental refinement: Sec. 4, Eq. (5), Figs. 5-6.
+ * Discretization and transfers: 7-point Laplacian, red-black Gauss-Seidel
+ * (red = (i+j+k) even, red first), mean-of-8 restriction, piecewise-constant
+ * V-cycle prolongation, trilinear FMG interpolation, exact coarsest solve.
+ *
+ * Conventions for every entry point:
+ *   - Grids are N^3 contiguous double arrays in DEVICE memory, element
+ *     [(k*N + j)*N + i] is cell (i,j,k) with center ((i+1/2)h, (j+1/2)h,
+ *     (k+1/2)h), h = 1/N (x fastest; a torch tensor of shape (N,N,N) indexed
+ *     [z,y,x]).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream); work
+ *     is enqueued asynchronously on it and no call synchronizes the device
+ *     except fmg_plan_create/destroy and fmg_solve.
+ *   - Return value: FMG_OK (0) or a negative fmg_status; the message of the
+ *     last failure on the calling thread is returned by fmg_last_error().
+ *     Parameter errors are detected on the host before anything is enqueued.
+ *     Nothing aborts the process.
+ */
+#ifndef FMG_H
+#define FMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMG_OK = 0,
+  FMG_EINVAL = -1, /* invalid argument (shape, schedule, pointer) */
+  FMG_ENOMEM = -2, /* device allocation failed */
+  FMG_EHIP = -3,   /* a HIP runtime call failed */
+  FMG_ENOTSUP = -4 /* valid but unsupported combination */
+} fmg_status;
+
+typedef enum {
+  FMG_FP64 = 0,        /* every operation in FP64 */
+  FMG_FP32_REFINED = 1 /* FP32 multigrid corrected by FP64 residuals */
+} fmg_precision;
+
+/*
+ * Solver parameters.
+ *   levels            total number of grids M+1 (Sec. 2): level 0 is the
+ *                     coarsest, edge n0 = N >> (levels-1), with
+ *                     n0 << (levels-1) == N and 1 <= n0 <= 8.
+ *   sr_levels         K: the K finest levels are solved by segmental
+ *                     refinement (Sec. 4); 0 = plain global FMG.
+ *                     0 <= K <= levels-1.  The transition level is
+ *                     T = levels-1-K.
+ *   segments_per_dim  S >= 1 segments per dimension (S^3 segments); needs
+ *                     N % (S << K) == 0 so that every segment owns at least
+ *                     one cell of the transition level.
+ *   buffer_schedule   HOST pointer to K buffer widths J, FINEST LEVEL FIRST
+ *                     (J for level levels-1, then levels-2, ...), each even
+ *                     and >= 0 (Eq. 5), and each at least half the width of
+ *                     the next finer level (the coarse support of a compute
+ *                     region must lie inside the coarser compute region).
+ *                     May be NULL when K == 0.  Copied at plan creation.
+ *   nu_pre, nu_post, alpha
+ *                     red-black sweeps before and after the coarse-grid
+ *                     correction and after each FMG interpolation (the
+ *                     F(alpha, nu1, nu2) cycle of Sec. 3.2); each 0..8.
+ *   precision         fmg_precision.
+ *   refine_iters      FP64 residual corrections for FMG_FP32_REFINED (0..8).
+ */
+typedef struct {
+  int32_t levels;
+  int32_t sr_levels;
+  int32_t segments_per_dim;
+  const int32_t *buffer_schedule;
+  int32_t nu_pre, nu_post, alpha;
+  int32_t precision;
+  int32_t refine_iters;
+} fmg_params;
+
+typedef struct fmg_plan fmg_plan;
+
+/* Host-only validation of (N, *p); no device call.  FMG_OK or FMG_EINVAL. */
+int32_t fmg_check_params(int32_t N, const fmg_params *p);
+
+/* Validate, select `device`, allocate all device workspace and precompute the
+ * coarsest-level inverse (in FP64 on the host).  On success *out owns the
+ * workspace until fmg_plan_destroy.  FMG_EINVAL, FMG_ENOMEM or FMG_EHIP on
+ * failure (then *out is NULL). */
+int32_t fmg_plan_create(int32_t N, const fmg_params *p, int32_t device, fmg_plan **out);
+
+/* Enqueue one solve on `stream`: u <- FMG(f) (Fig. 2 for sr_levels == 0,
+ * Fig. 5 otherwise).  f, u: device pointers to N^3 doubles; u is fully
+ * overwritten (its prior content is ignored); f is read only and must stay
+ * valid until the stream passes the solve.  f and u must not overlap.  A plan
+ * serves one stream at a time and is not thread-safe. */
+int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *stream);
+
+/* Free the workspace (synchronizes the plan's device).  NULL is accepted. */
+int32_t fmg_plan_destroy(fmg_plan *plan);
+
+/* create + execute + stream synchronize + destroy. */
+int32_t fmg_solve(const double *f, int32_t N, const fmg_params *p, double *u, void *stream);
+
+/* Device bytes held by the plan. */
+int64_t fmg_plan_workspace_bytes(const fmg_plan *plan);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char *fmg_last_error(void);
+
+/*
+ * Single operators on one whole level of edge n (device arrays of n^3
+ * doubles, layout as above), enqueued on `stream`.  They run the same
+ * kernels as the solver and exist to test them one by one.
+ *   fmg_op_apply:    out = L_h u                      (Eq. 2, 7-point)
+ *   fmg_op_smooth:   nu red-black Gauss-Seidel sweeps on u for L_h u = rhs
+ *   fmg_op_restrict: coarse ((n/2)^3) = mean of the 8 children of fine (n^3)
+ *   fmg_op_interp:   fine ((2n)^3) = trilinear FMG interpolation of coarse
+ *                    (n^3), odd reflection at the walls (Sec. 3.2)
+ */
+int32_t fmg_op_apply(const double *u, int32_t n, double *out, void *stream);
+int32_t fmg_op_smooth(double *u, const double *rhs, int32_t n, int32_t nu, void *stream);
+int32_t fmg_op_restrict(const double *fine, int32_t n, double *coarse, void *stream);
+int32_t fmg_op_interp(const double *coarse, int32_t n, double *fine, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMG_H */

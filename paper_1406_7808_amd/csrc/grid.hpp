@@ -1,0 +1,74 @@
+// grid.hpp -- level and segment geometry shared by the host schedule and the
+// device kernels.
+//
+// Every level of the hierarchy is stored as one or more boxes.  A global level
+// (Sec. 3.3 of the paper, the conventional solver up to the transition level)
+// is a single unpadded n^3 box.  A segmental-refinement level (Sec. 4) holds
+// S^3 boxes, one per segment p = (px,py,pz): the compute region
+//   C = [max(0, p g - J), min(n, (p+1) g + J))   per dimension, g = n / S,
+// grown by one ghost layer (ghost cells inside the domain are the frozen GSR
+// cells, those outside are boundary ghosts and are never touched).  All boxes
+// of a level share the edge m = min(n, g + 2J) + 2 so segment q starts at
+// element q * m^3; clipped boxes leave their tail unused.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fmg {
+
+struct Geo {
+  int n;          // level edge: the domain is cells [0, n)^3 of this level
+  int S;          // segments per dimension (1 for a global level)
+  int g;          // genuine edge n / S
+  int J;          // buffer width
+  int m;          // storage edge per dimension
+  int ghost;      // 1: storage starts one cell before C; 0: unpadded global
+  long long sstride;  // elements from one segment's box to the next
+};
+
+struct Box {
+  int a[3];   // compute region start (global level indices)
+  int b[3];   // compute region end (exclusive)
+  int o[3];   // global index of storage element (0,0,0)
+  long long base;
+};
+
+__host__ __device__ inline Geo global_geo(int n) {
+  Geo G;
+  G.n = n; G.S = 1; G.g = n; G.J = 0; G.m = n; G.ghost = 0;
+  G.sstride = (long long)n * n * n;
+  return G;
+}
+
+__host__ __device__ inline Geo segment_geo(int n, int S, int J) {
+  Geo G;
+  G.n = n; G.S = S; G.g = n / S; G.J = J;
+  G.m = ((G.g + 2 * J) < n ? (G.g + 2 * J) : n) + 2;
+  G.ghost = 1;
+  G.sstride = (long long)G.m * G.m * G.m;
+  return G;
+}
+
+// box of segment q (q is ignored on a global level)
+__host__ __device__ inline Box seg_box(const Geo& G, int q) {
+  Box B;
+  int s = (G.S > 1) ? q : 0;
+  int p[3] = {s % G.S, (s / G.S) % G.S, s / (G.S * G.S)};
+  for (int d = 0; d < 3; ++d) {
+    int a = p[d] * G.g - G.J, b = (p[d] + 1) * G.g + G.J;
+    B.a[d] = a < 0 ? 0 : a;
+    B.b[d] = b > G.n ? G.n : b;
+    B.o[d] = B.a[d] - G.ghost;
+  }
+  B.base = (long long)s * G.sstride;
+  return B;
+}
+
+__host__ __device__ inline long long at(const Geo& G, const Box& B, int i, int j, int k) {
+  return B.base + ((long long)(k - B.o[2]) * G.m + (j - B.o[1])) * G.m + (i - B.o[0]);
+}
+
+__host__ __device__ inline bool in_dom(int n, int i, int j, int k) {
+  return (unsigned)i < (unsigned)n && (unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n;
+}
+
+}  // namespace fmg

@@ -1,0 +1,185 @@
+"""Python binding of the HIP solver library (include/fmg.h).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+``libfmg.so``.  torch supplies device memory and the current stream.  There
+is no fallback: if the library is missing, importing a function raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libfmg.so")
+
+FMG_OK, FMG_EINVAL, FMG_ENOMEM, FMG_EHIP, FMG_ENOTSUP = 0, -1, -2, -3, -4
+PRECISION = {"fp64": 0, "fp32_refined": 1}
+
+
+class FMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fmg status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("sr_levels", ctypes.c_int32),
+        ("segments_per_dim", ctypes.c_int32),
+        ("buffer_schedule", ctypes.POINTER(ctypes.c_int32)),
+        ("nu_pre", ctypes.c_int32),
+        ("nu_post", ctypes.c_int32),
+        ("alpha", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32),
+    ]
+
+
+_lib = None
+SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_destroy",
+           "fmg_solve", "fmg_plan_workspace_bytes", "fmg_last_error", "fmg_op_apply",
+           "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
+
+
+def lib():
+    """Load libfmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise ImportError("HIP library %s is missing: run __graft_entry__.build()" % _SO)
+    L = ctypes.CDLL(_SO)
+    vp, i32, pp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Params)
+    L.fmg_check_params.argtypes = [i32, pp]
+    L.fmg_check_params.restype = i32
+    L.fmg_plan_create.argtypes = [i32, pp, i32, ctypes.POINTER(vp)]
+    L.fmg_plan_create.restype = i32
+    L.fmg_plan_execute.argtypes = [vp, vp, vp, vp]
+    L.fmg_plan_execute.restype = i32
+    L.fmg_plan_destroy.argtypes = [vp]
+    L.fmg_plan_destroy.restype = i32
+    L.fmg_solve.argtypes = [vp, i32, pp, vp, vp]
+    L.fmg_solve.restype = i32
+    L.fmg_plan_workspace_bytes.argtypes = [vp]
+    L.fmg_plan_workspace_bytes.restype = ctypes.c_int64
+    L.fmg_last_error.argtypes = []
+    L.fmg_last_error.restype = ctypes.c_char_p
+    L.fmg_op_apply.argtypes = [vp, i32, vp, vp]
+    L.fmg_op_smooth.argtypes = [vp, vp, i32, i32, vp]
+    L.fmg_op_restrict.argtypes = [vp, i32, vp, vp]
+    L.fmg_op_interp.argtypes = [vp, i32, vp, vp]
+    for name in ("fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != FMG_OK:
+        raise FMGError(st, lib().fmg_last_error().decode())
+
+
+def make_params(levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",
+                refine_iters=2):
+    """fmg_params; sweeps = (nu_pre, nu_post, alpha); buffers finest first.
+    Returns (params, keepalive) -- keep the second alive while params is used."""
+    J = (ctypes.c_int32 * max(1, len(buffers)))(*buffers)
+    p = _Params(levels, sr_levels, segments,
+                ctypes.cast(J, ctypes.POINTER(ctypes.c_int32)) if len(buffers) else None,
+                sweeps[0], sweeps[1], sweeps[2], PRECISION[precision], refine_iters)
+    return p, J
+
+
+def check_params(N, **kw):
+    """Host-only validation; returns (status, message)."""
+    p, keep = make_params(**kw)
+    st = lib().fmg_check_params(N, ctypes.byref(p))
+    return st, (lib().fmg_last_error().decode() if st else "")
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, N=None):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise FMGError(FMG_EINVAL, "expected a contiguous float64 CUDA tensor")
+    if N is not None and tuple(t.shape) != (N, N, N):
+        raise FMGError(FMG_EINVAL, "expected shape (%d, %d, %d)" % (N, N, N))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan: validated parameters plus all device workspace."""
+
+    def __init__(self, N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1),
+                 precision="fp64", refine_iters=2, device=None):
+        self.N = N
+        self._p, self._keep = make_params(levels, sr_levels, segments, buffers, sweeps, precision,
+                                          refine_iters)
+        dev = torch.cuda.current_device() if device is None else device
+        self.device = torch.device("cuda", dev)
+        h = ctypes.c_void_p()
+        _check(lib().fmg_plan_create(N, ctypes.byref(self._p), dev, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def workspace_bytes(self):
+        return lib().fmg_plan_workspace_bytes(self._h)
+
+    def execute(self, f, u=None, stream=None):
+        """Enqueue u <- FMG(f) on the stream (default: torch's current)."""
+        if u is None:
+            u = torch.empty_like(f)
+        _check(lib().fmg_plan_execute(self._h, _dev(f, self.N), _dev(u, self.N), _stream(stream)))
+        return u
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fmg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(f, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",
+          refine_iters=2):
+    """u = FMG(f) for a (N, N, N) float64 CUDA tensor f (synchronous)."""
+    N = f.shape[0]
+    u = torch.empty_like(f)
+    p, keep = make_params(levels, sr_levels, segments, buffers, sweeps, precision, refine_iters)
+    _check(lib().fmg_solve(_dev(f, N), N, ctypes.byref(p), _dev(u, N), _stream(None)))
+    return u
+
+
+def op_apply(u):
+    out = torch.empty_like(u)
+    _check(lib().fmg_op_apply(_dev(u, u.shape[0]), u.shape[0], _dev(out), _stream(None)))
+    return out
+
+
+def op_smooth(u, rhs, nu):
+    """nu red-black sweeps on u in place."""
+    _check(lib().fmg_op_smooth(_dev(u, u.shape[0]), _dev(rhs, u.shape[0]), u.shape[0], nu,
+                               _stream(None)))
+    return u
+
+
+def op_restrict(v):
+    n = v.shape[0]
+    out = torch.empty((n // 2,) * 3, dtype=v.dtype, device=v.device)
+    _check(lib().fmg_op_restrict(_dev(v, n), n, _dev(out), _stream(None)))
+    return out
+
+
+def op_interp(v):
+    n = v.shape[0]
+    out = torch.empty((2 * n,) * 3, dtype=v.dtype, device=v.device)
+    _check(lib().fmg_op_interp(_dev(v, n), n, _dev(out), _stream(None)))
+    return out

@@ -1,0 +1,79 @@
+"""The C interface on the host (no GPU needed): the library loads, exports
+every function that include/fmg.h declares, and validates parameters before
+any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1406_7808_amd import fmg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert "fmg_plan_execute" in names and len(names) >= 10
+    lib = ctypes.CDLL(fmg._SO)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    assert sorted(fmg.SYMBOLS) == _declared()
+
+
+def _chk(N, **kw):
+    base = dict(levels=5, sr_levels=2, segments=2, buffers=(2, 2))
+    base.update(kw)
+    return fmg.check_params(N, **base)
+
+
+def test_valid_parameters():
+    assert _chk(32)[0] == 0
+    assert _chk(256, levels=8, sr_levels=3, segments=8, buffers=(2, 4, 6))[0] == 0
+    assert _chk(512, levels=8, sr_levels=3, segments=16, buffers=(2, 4, 6))[0] == 0
+    assert _chk(96, levels=6, sr_levels=2, segments=3, buffers=(2, 2))[0] == 0
+    assert _chk(32, sr_levels=0, segments=1, buffers=())[0] == 0
+    assert _chk(1, levels=1, sr_levels=0, segments=1, buffers=())[0] == 0
+
+
+@pytest.mark.parametrize("N,kw,frag", [
+    (32, dict(buffers=(3, 2)), "even"),
+    (32, dict(buffers=(-2, 2)), "even"),
+    (32, dict(buffers=(8, 2)), "half"),
+    (32, dict(segments=3), "divisible"),
+    (32, dict(segments=8, sr_levels=3, buffers=(2, 2, 2)), "divisible"),
+    (32, dict(levels=2, sr_levels=0, buffers=()), "coarsest"),
+    (30, dict(), "n0"),
+    (32, dict(sr_levels=5, buffers=(2,) * 5), "sr_levels"),
+    (32, dict(sweeps=(9, 2, 1)), "nu_pre"),
+    (32, dict(segments=0), "segments_per_dim"),
+    (32, dict(levels=0), "levels"),
+])
+def test_invalid_parameters_are_rejected(N, kw, frag):
+    st, msg = _chk(N, **kw)
+    assert st == fmg.FMG_EINVAL
+    assert frag in msg
+
+
+def test_null_buffer_schedule_rejected():
+    p, keep = fmg.make_params(5, 2, 2, ())
+    st = fmg.lib().fmg_check_params(32, ctypes.byref(p))
+    assert st == fmg.FMG_EINVAL
+    assert b"buffer_schedule" in fmg.lib().fmg_last_error()
+
+
+def test_null_params_and_plan():
+    L = fmg.lib()
+    assert L.fmg_check_params(32, None) == fmg.FMG_EINVAL
+    assert L.fmg_plan_destroy(None) == 0
+    assert L.fmg_plan_execute(None, None, None, None) == fmg.FMG_EINVAL
+    assert L.fmg_plan_workspace_bytes(None) == 0

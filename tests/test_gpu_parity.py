@@ -1,0 +1,202 @@
+"""GPU parity: the HIP library (through its C interface) against the FP64 oracle.
+
+FP64 bar: ||u_gpu - u_oracle||_inf <= 1e-12 ||u_oracle||_inf.  Both sides
+follow the same operation order up to fused multiply-add contraction and the
+summation order of a few sums, and FMG damps such rounding, so observed
+differences are near 1e-15.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.exact as ex
+from paper_1406_7808_amd import fmg
+from paper_1406_7808_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _rel(a, b):
+    a = a.cpu().numpy() if torch.is_tensor(a) else a
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# --- single operators ----------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 33])
+def test_op_apply(n):
+    _say("op_apply", n)
+    u = W.random_field(n, 100 + n)
+    got = fmg.op_apply(_gpu(u))
+    assert _rel(got, oracle.apply(u)) <= 1e-14
+
+
+@pytest.mark.parametrize("n,nu", [(4, 1), (16, 2), (33, 1), (64, 3)])
+def test_op_smooth(n, nu):
+    _say("op_smooth", n, nu)
+    u = W.random_field(n, 200 + n)
+    f = W.random_field(n, 300 + n) * n * n
+    got = fmg.op_smooth(_gpu(u), _gpu(f), nu)
+    assert _rel(got, oracle.smooth(u, f, nu)) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 6, 32])
+def test_op_restrict(n):
+    _say("op_restrict", n)
+    v = W.random_field(n, 400 + n)
+    assert _rel(fmg.op_restrict(_gpu(v)), oracle.restrict(v)) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 3, 16])
+def test_op_interp(n):
+    _say("op_interp", n)
+    v = W.random_field(n, 500 + n)
+    assert _rel(fmg.op_interp(_gpu(v)), oracle.interp(v)) <= 1e-15
+
+
+# --- global FMG ----------------------------------------------------------------
+
+@pytest.mark.parametrize("N,L", [(2, 1), (8, 3), (32, 5), (48, 5), (40, 4), (64, 6), (96, 6)])
+def test_global_fmg_random(N, L):
+    _say("global", N, L)
+    f = W.random_field(N, N + L)
+    u = fmg.solve(_gpu(f), L)
+    assert _rel(u, oracle.fmg(f, L)) <= TOL
+
+
+def test_global_fmg_sine_32():
+    f, uc = W.sine(32)
+    u = fmg.solve(_gpu(f), 5).cpu().numpy()
+    assert _rel(u, oracle.fmg(f, 5)) <= TOL
+    ed = np.abs(uc * ex.sine_discrete(32) - uc).max()
+    assert np.abs(u - uc * ex.sine_discrete(32)).max() <= 0.6 * ed
+
+
+@pytest.mark.parametrize("sweeps", [(1, 1, 0), (3, 1, 2), (0, 2, 1)])
+def test_global_fmg_sweep_counts(sweeps):
+    N, L = 32, 5
+    f = W.random_field(N, 7)
+    u = fmg.solve(_gpu(f), L, sweeps=sweeps)
+    assert _rel(u, oracle.fmg(f, L, alpha=sweeps[2], nu1=sweeps[0], nu2=sweeps[1])) <= TOL
+
+
+# --- segmental refinement --------------------------------------------------------
+
+SR_CASES = [
+    (32, 5, 2, 2, [2, 2]),        # the small workload's SR setting
+    (32, 5, 3, 2, [2, 4, 6]),
+    (32, 5, 4, 2, [2, 2, 2, 2]),  # transition level is the coarsest
+    (32, 5, 2, 4, [4, 2]),
+    (32, 5, 1, 4, [0]),           # no buffer at all
+    (32, 5, 2, 1, [2, 2]),        # one segment
+    (32, 5, 2, 2, [16, 8]),       # ample buffers
+    (64, 6, 3, 2, [2, 4, 6]),
+    (64, 6, 2, 4, [6, 4]),
+    (48, 5, 2, 2, [2, 2]),        # coarsest edge 3
+    (96, 6, 2, 3, [2, 2]),        # odd segment count
+]
+
+
+@pytest.mark.parametrize("N,L,K,S,J", SR_CASES)
+def test_sr_fmg_random(N, L, K, S, J):
+    _say("sr", N, L, K, S, J)
+    f = W.random_field(N, N + 10 * K + S)
+    u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J)
+    assert _rel(u, oracle.srfmg(f, L, K, S, J)) <= TOL
+
+
+def test_sr_fmg_small_workload_sine():
+    f, uc = W.sine(32)
+    ug = fmg.solve(_gpu(f), 5).cpu().numpy()
+    us = fmg.solve(_gpu(f), 5, sr_levels=2, segments=2, buffers=[2, 2]).cpu().numpy()
+    assert _rel(us, oracle.srfmg(f, 5, 2, 2, [2, 2])) <= TOL
+    assert _rel(ug, oracle.fmg(f, 5)) <= TOL
+
+
+# --- full size (256^3, 8 levels, 8^3 segments, buffers 2,4,6) --------------------
+
+@pytest.fixture(scope="module")
+def fourier256():
+    f, uc, (k, a) = W.fourier(256)
+    return f, uc, k, a
+
+
+def test_full_size_global(fourier256):
+    f = fourier256[0]
+    _say("full global 256")
+    u = fmg.solve(_gpu(f), 8)
+    assert _rel(u, oracle.fmg(f, 8)) <= TOL
+
+
+def test_full_size_sr(fourier256):
+    f = fourier256[0]
+    _say("full sr 256")
+    plan = fmg.Plan(256, 8, sr_levels=3, segments=8, buffers=[2, 4, 6])
+    fg = _gpu(f)
+    u = plan.execute(fg)
+    torch.cuda.synchronize()
+    ref = oracle.srfmg(f, 8, 3, 8, [2, 4, 6])
+    assert _rel(u, ref) <= TOL
+    # a second execution of the same plan overwrites u completely
+    u2 = plan.execute(fg, torch.full_like(fg, float("nan")))
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2)
+    plan.close()
+
+
+# --- mixed precision --------------------------------------------------------------
+
+@pytest.mark.parametrize("N,L,K,S,J", [(64, 6, 2, 2, [2, 2]), (64, 6, 0, 1, []),
+                                        (256, 8, 3, 8, [2, 4, 6])])
+def test_fp32_refined_within_discretization_error(N, L, K, S, J):
+    _say("fp32r", N, L, K, S, J)
+    f, uc, (k, a) = W.fourier(N)
+    ud = W.fourier_field(N, k, ex.modes_discrete(N, k, a))
+    edisc = np.abs(ud - uc).max()
+    u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J, precision="fp32_refined",
+                  refine_iters=2).cpu().numpy()
+    assert np.abs(u - ud).max() <= 1.0 * edisc
+    # the same outer iteration run entirely in FP64 by the oracle: the FP32
+    # inner solves change each correction by a relative O(1e-6) at most
+    ref = oracle.srfmg_refined(f, L, K, S, J, iters=2) if K else None
+    if ref is not None:
+        assert np.abs(u - ref).max() <= 1e-3 * edisc
+
+
+# --- determinism and plan reuse ---------------------------------------------------
+
+def test_determinism_and_reuse():
+    N, L = 64, 6
+    plan = fmg.Plan(N, L, sr_levels=2, segments=4, buffers=[4, 4])
+    f1 = _gpu(W.random_field(N, 1))
+    f2 = _gpu(W.random_field(N, 2))
+    a = plan.execute(f1).clone()
+    b = plan.execute(f2).clone()
+    c = plan.execute(f1).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    assert _rel(b, oracle.srfmg(f2.cpu().numpy(), L, 2, 4, [4, 4])) <= TOL
+
+
+def test_invalid_arguments_raise_before_launch():
+    f = _gpu(np.zeros((32, 32, 32)))
+    with pytest.raises(fmg.FMGError) as e:
+        fmg.solve(f, 5, sr_levels=2, segments=2, buffers=[3, 2])
+    assert e.value.status == fmg.FMG_EINVAL
+    plan = fmg.Plan(32, 5)
+    with pytest.raises(fmg.FMGError):
+        plan.execute(f, f)  # aliasing f and u
+    plan.close()
