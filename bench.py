@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""FMG solve throughput on one MI355X.
+
+Workload (the 256^3 case): 3D Poisson, cell-centered 7-point, u = 0 on the
+unit cube, FP64; FMG F(1,2,2) with 8 levels (256 -> 2), red-black
+Gauss-Seidel, mean-of-8 restriction, piecewise-constant V-cycle
+prolongation, trilinear FMG interpolation; right-hand side = 64 seeded random
+sine modes (k_d ~ U{1..16}, amplitude z/|k|^2, seed 14067808).
+
+One step = one solve.  Three solvers are timed on the same right-hand side:
+  sr     segmental refinement on the 3 finest levels, 8^3 segments, buffer
+         widths 2, 4, 6 from the finest level up (the headline `value`);
+  global plain global FMG;
+  sr32r  the same SR solve with FP32 multigrid and 2 FP64 residual
+         corrections.
+`value` = N^3 / (time of one SR solve), inputs resident in HBM.
+
+Also reported: the dominant kernel's roofline (HIP events around each of its
+launches in a profiled pass, algorithmic bytes from the launch geometry), the
+CPU oracle's throughput on a bounded sample, and the accuracy of each solver
+against the closed-form discrete solution.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, LEVELS, K, S, J = 256, 8, 3, 8, (2, 4, 6)
+METRIC = "FMG solve DOF/s + % HBM peak at 256^3 (global vs SR vs FP32-refined SR)"
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1406_7808_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launches_bytes):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
+    summaries (profiles/traffic.json), or None when absent or taken on
+    other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash() or t.get("kernel") != kernel:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--variants", default="sr,global,sr32r")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this solver runs on one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1406_7808_amd import fmg
+    from paper_1406_7808_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    f, ucont, (kk, aa) = W.fourier(N)
+    fd = torch.from_numpy(f).to(dev)
+    print("bench: inputs ready (%.1fs)" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    specs = {
+        "sr": dict(sr_levels=K, segments=S, buffers=J),
+        "global": dict(),
+        "sr32r": dict(sr_levels=K, segments=S, buffers=J, precision="fp32_refined",
+                      refine_iters=2),
+    }
+    names = [v for v in args.variants.split(",") if v]
+    res, outs, plans = {}, {}, {}
+    for name in names:
+        plan = fmg.Plan(N, LEVELS, **specs[name])
+        plans[name] = plan
+        u = torch.empty_like(fd)
+        for _ in range(max(1, args.warmup)):
+            plan.execute(fd, u)
+        torch.cuda.synchronize()
+        graph = None
+        if not args.no_graph:
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                plan.execute(fd, u)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                plan.execute(fd, u)
+            graph.replay()
+            torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            if graph is not None:
+                graph.replay()
+            else:
+                plan.execute(fd, u)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[name] = {"ms": round(ms, 4), "dof_per_s": N ** 3 / (ms * 1e-3),
+                     "workspace_MB": round(plan.workspace_bytes / 2 ** 20, 1),
+                     "graph": graph is not None}
+        outs[name] = u.cpu().numpy()
+        print("bench: %s %.3f ms/solve" % (name, ms), file=sys.stderr, flush=True)
+        del graph
+
+    # dominant kernel of the headline solve: event-timed launches
+    head = names[0]
+    plan = plans[head]
+    plan.profile(True)
+    u = torch.empty_like(fd)
+    for _ in range(3):
+        plan.execute(fd, u)
+    stats = plan.profile_read()
+    plan.profile(False)
+    # the dominant kernel: largest total time over all its levels
+    by_kernel = {}
+    for k, v in stats.items():
+        name = k.split("@")[0]
+        a = by_kernel.setdefault(name, [0, 0.0, 0.0])
+        for i in range(3):
+            a[i] += v[i]
+    kern = max(by_kernel, key=lambda k: by_kernel[k][1])
+    launches, tot_ms, tot_bytes = by_kernel[kern]
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kern, tot_bytes / launches)
+    kernels = {k: {"launches": v[0] // 3, "ms_per_solve": round(v[1] / 3, 4),
+                   "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "launches_per_solve": launches // 3,
+                "avg_launch_us": round(tot_ms / launches * 1e3, 2),
+                "bytes_per_launch": tot_bytes / launches}
+
+    # accuracy against the closed-form discrete solution
+    import oracle.exact as ex  # closed forms only (test infrastructure)
+    ud = W.fourier_field(N, kk, ex.modes_discrete(N, kk, aa))
+    edisc = float(np.abs(ud - ucont).max())
+    acc = {"e_disc": edisc}
+    for name, u in outs.items():
+        acc[name] = {"e_alg_over_e_disc": float(np.abs(u - ud).max() / edisc),
+                     "e_total": float(np.abs(u - ucont).max())}
+    if "sr" in outs and "global" in outs:
+        acc["e_r_sr_over_global"] = acc["sr"]["e_total"] / acc["global"]["e_total"]
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        ref, reps, tc = None, 0, time.time()
+        while reps < 4 and (reps == 0 or time.time() - tc < 10.0):
+            ref = oracle.srfmg(f, LEVELS, K, S, list(J))
+            reps += 1
+        el = time.time() - tc
+        cpu = {"value": reps * N ** 3 / el, "unit": "DOF/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": "%d SR-FMG FP64 solve(s) of the same 256^3 workload, %.1f s" % (reps, el)}
+        if "sr" in outs:
+            acc["sr_parity_rel_vs_oracle"] = float(np.abs(outs["sr"] - ref).max()
+                                                   / np.abs(ref).max())
+
+    head_ms = res[head]["ms"]
+    out = {
+        "metric": METRIC,
+        "value": N ** 3 / (head_ms * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson3d-256^3-fp64-srfmg", "N": N, "levels": LEVELS,
+                   "sr_levels": K, "segments_per_dim": S, "buffers_finest_first": list(J),
+                   "cycle": "F(1,2,2)", "rhs": "64 sine modes, seed 14067808",
+                   "headline": head},
+        "variants": res,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+    }
+    for p in plans.values():
+        p.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -110,6 +110,44 @@ int32_t fmg_solve(const double *f, int32_t N, const fmg_params *p, double *u, vo
 /* Device bytes held by the plan. */
 int64_t fmg_plan_workspace_bytes(const fmg_plan *plan);
 
+/*
+ * Kernel timing.  While enabled, every launch enqueued by fmg_plan_execute
+ * is bracketed by two HIP events on the solve's stream; fmg_plan_profile_read
+ * waits for the last one, aggregates per kernel name and level ("name@level",
+ * level 0 = coarsest; no suffix for whole-grid steps) and clears the records.
+ * `bytes` sums the algorithmic bytes of the launches: the cells each launch
+ * must read and write at least once (one read of every input cell it uses, one
+ * write of every output cell), independent of caching.
+ */
+typedef struct {
+  char name[64];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} fmg_kernel_stat;
+
+/* Enable (1) or disable (0) timing; pending records are discarded. */
+int32_t fmg_plan_profile(fmg_plan *plan, int32_t enable);
+
+/* Copy up to `cap` per-kernel aggregates to out and their number to *count
+ * (synchronizes with the last timed launch). */
+int32_t fmg_plan_profile_read(fmg_plan *plan, fmg_kernel_stat *out, int32_t cap, int32_t *count);
+
+/*
+ * Schedule model (host only, no device call): walks the launches of one
+ * fmg_plan_execute for (N, *p) on a virtual workspace, checking every
+ * launch's pointers and grid, and returns the launch count, the sum of their
+ * algorithmic bytes (as in fmg_kernel_stat) and the workspace a plan would
+ * allocate.
+ */
+typedef struct {
+  int64_t launches;
+  double bytes;
+  int64_t workspace_bytes;
+} fmg_schedule_stat;
+
+int32_t fmg_schedule_model(int32_t N, const fmg_params *p, fmg_schedule_stat *out);
+
 /* Message of the last non-OK status returned on this thread ("" if none). */
 const char *fmg_last_error(void);
 
@@ -119,6 +157,8 @@ const char *fmg_last_error(void);
  * kernels as the solver and exist to test them one by one.
  *   fmg_op_apply:    out = L_h u                      (Eq. 2, 7-point)
  *   fmg_op_smooth:   nu red-black Gauss-Seidel sweeps on u for L_h u = rhs
+ *                    (allocates a temporary copy of u and synchronizes
+ *                    `stream` before returning)
  *   fmg_op_restrict: coarse ((n/2)^3) = mean of the 8 children of fine (n^3)
  *   fmg_op_interp:   fine ((2n)^3) = trilinear FMG interpolation of coarse
  *                    (n^3), odd reflection at the walls (Sec. 3.2)

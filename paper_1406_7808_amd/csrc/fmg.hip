@@ -23,6 +23,8 @@
 
 #include "../../include/fmg.h"
 #include "grid.hpp"
+#include "kernels_coarse.hpp"
+#include "kernels_fused.hpp"
 #include "kernels_simple.hpp"
 
 using namespace fmg;
@@ -45,7 +47,6 @@ static void hipcheck(hipError_t e, const char* what) {
   if (e != hipSuccess) throw hip_error(std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define LAUNCH_CHECK(name) hipcheck(hipGetLastError(), name)
 
 // ---------------------------------------------------------------------------
 // parameter validation (host only)
@@ -164,16 +165,68 @@ template <class T>
 struct Hier {
   std::vector<Geo> geo;          // storage geometry of u, t, rhs on each level
   std::vector<T*> u, t, rhs, f;  // f[l]: global right-hand-side hierarchy
+  // The temporally blocked smoother reads one copy of u and writes the other
+  // (tiles overlap by their halo, so an in-place update would race); u[l] is
+  // the current copy, ua[l] / ub[l] the pair.
+  std::vector<T*> ua, ub;
+};
+
+// Per-launch timing: when enabled, every launch of a solve is bracketed by two
+// HIP events on the solve's stream and tagged with its kernel name and the
+// algorithmic bytes it must move (the unique cells it reads and writes).
+struct Prof {
+  struct Rec {
+    const char* name;
+    int level;  // -1: not tied to one level
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool on = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipcheck(hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+  void recycle() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~Prof() {
+    recycle();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 struct fmg_plan {
   int N = 0, L = 0, K = 0, T = 0, S = 1, n0 = 1, device = 0;
   int nu1 = 2, nu2 = 2, alpha = 1, precision = FMG_FP64, refine = 2;
+  bool fused = true;          // temporally blocked smoother (else single-cell kernels)
+  int Lc = 0;                 // global levels 0..Lc run in the persistent coarse kernel
+  int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
+  long long target_blocks = 1024;  // workgroups a fused launch aims for
+  int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
   Hier<double> h64;
   Hier<float> h32;
   double* Ainv = nullptr;
+  double* ws_finest = nullptr;  // second copy of the finest global FP64 level
+  bool finest_odd = false;      // the finest level ends in its second copy
   float* r32 = nullptr;  // FP32 right-hand side of the inner solves
+  Prof prof;
+  bool virt = false;              // workspace is virtual (schedule model only)
+  uintptr_t virt_next = 1 << 20;  // next virtual address
+  long long model_launches = 0;   // launches walked by a dry run
+  double model_bytes = 0;         // their algorithmic bytes
   std::vector<void*> allocs;
   std::vector<size_t> sizes;
   long long bytes = 0;
@@ -182,6 +235,12 @@ struct fmg_plan {
 static void* dalloc(fmg_plan* P, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) return nullptr;
+  if (P->virt) {  // schedule model: distinct non-null addresses, no device memory
+    p = (void*)P->virt_next;
+    P->virt_next += (bytes + 255) / 256 * 256;
+    P->bytes += (long long)bytes;
+    return p;
+  }
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     throw std::bad_alloc();
@@ -199,6 +258,8 @@ static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
   int L = P->L;
   H.geo.resize(L);
   H.u.assign(L, nullptr);
+  H.ua.assign(L, nullptr);
+  H.ub.assign(L, nullptr);
   H.t.assign(L, nullptr);
   H.rhs.assign(L, nullptr);
   H.f.assign(L, nullptr);
@@ -208,8 +269,10 @@ static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
     H.geo[l] = sr ? segment_geo(n, P->S, P->J[l]) : global_geo(n);
     long long cnt = sr ? cube(P->S) * H.geo[l].sstride : cube(n);
     if (l < L - 1) H.f[l] = (T*)dalloc(P, sizeof(T) * cube(n));
-    if (l == L - 1 && !sr && finest_external) continue;  // caller's array
-    H.u[l] = (T*)dalloc(P, sizeof(T) * cnt);
+    // the caller's array is one copy of the finest global level
+    if (!(l == L - 1 && !sr && finest_external)) H.ua[l] = (T*)dalloc(P, sizeof(T) * cnt);
+    if (l > 0) H.ub[l] = (T*)dalloc(P, sizeof(T) * cnt);
+    H.u[l] = H.ua[l];
     if (l < L - 1) {
       H.t[l] = (T*)dalloc(P, sizeof(T) * cnt);
       H.rhs[l] = (T*)dalloc(P, sizeof(T) * cnt);
@@ -226,92 +289,322 @@ static dim3 grid_for(long long cells, int nseg) {
   return dim3((unsigned)((cells + kBlock - 1) / kBlock), (unsigned)nseg);
 }
 
+// planes in flight per thread in the temporally blocked smoother: one plane,
+// whose loads overlap the half-sweeps of a whole step (deeper rings make the
+// register allocator copy in-flight registers at the loop back edge)
+template <int NS>
+constexpr int kPrefetch = 1;
+
+template <class X>
+static bool nonnull(const X&) { return true; }
+template <class X>
+static bool nonnull(X* p) { return p != nullptr; }
+template <class X>
+static bool nonnull(const SmoothArgs<X>& a) {
+  return a.uin && a.u && a.rhs && a.uin != a.u;
+}
+template <class X>
+static bool nonnull(const BoxArgs<X>& a) { return a.u && a.rhs && a.d; }
+template <class X>
+static bool nonnull(const CoarseArgs<X>& a) {
+  if (!a.Ainv || !a.u[0] || (a.mode == 1 && !a.rt)) return false;
+  for (int l = 0; l <= a.top; ++l) {
+    if (!a.u[l] || (a.mode == 0 && !a.f[l])) return false;
+    if (l < a.top && (!a.t[l] || !a.r[l])) return false;
+  }
+  return true;
+}
+
 template <class T>
 struct Exec {
   using A = T;  // smoothing arithmetic: FP64 or FP32
   fmg_plan* P;
   Hier<T>& H;
   hipStream_t s;
+  bool dry = false;  // walk the schedule without launching (buffer bookkeeping)
+  int lvl = -1;      // level of the launches being issued (profile label)
 
   int nseg(int l) const { return l > P->T ? P->S * P->S * P->S : 1; }
+
+  template <class K, class... Args>
+  void run(const char* name, double bytes, dim3 grid, dim3 block, K kern, Args... args) {
+    run_shm(name, bytes, grid, block, 0, kern, args...);
+  }
+
+  template <class K, class... Args>
+  void run_shm(const char* name, double bytes, dim3 grid, dim3 block, size_t shm, K kern,
+               Args... args) {
+    if (!(nonnull(args) && ...)) throw hip_error(std::string("internal: null pointer for ") + name);
+    if (grid.x == 0 || grid.y == 0) throw hip_error(std::string("internal: empty grid for ") + name);
+    if (dry) {
+      P->model_launches += 1;
+      P->model_bytes += bytes;
+      return;
+    }
+    Prof& pr = P->prof;
+    hipEvent_t a = nullptr;
+    if (pr.on) {
+      a = pr.get();
+      hipcheck(hipEventRecord(a, s), "hipEventRecord");
+    }
+    hipLaunchKernelGGL(kern, grid, block, shm, s, args...);
+    hipcheck(hipGetLastError(), name);
+    if (pr.on) {
+      hipEvent_t b = pr.get();
+      hipcheck(hipEventRecord(b, s), "hipEventRecord");
+      pr.recs.push_back({name, lvl, a, b, bytes});
+    }
+  }
   int cext(int l) const {  // maximal compute-region edge
     const Geo& G = H.geo[l];
     return (G.g + 2 * G.J) < G.n ? (G.g + 2 * G.J) : G.n;
   }
 
-  void smooth(int l, const T* rhs, Geo gr, int nu) {
+  // cells summed over all segments of a level: compute regions, and stored
+  // cells inside the domain (compute regions plus GSR ghosts)
+  static double span_sum(const Geo& G, int grow) {
+    double t = 0;
+    for (int p = 0; p < G.S; ++p) {
+      int a = p * G.g - G.J - grow, b = (p + 1) * G.g + G.J + grow;
+      t += (b > G.n ? G.n : b) - (a < 0 ? 0 : a);
+    }
+    return t;
+  }
+  static double c_cells(const Geo& G) { double t = span_sum(G, 0); return t * t * t; }
+  static double st_cells(const Geo& G) { double t = span_sum(G, G.ghost); return t * t * t; }
+
+  // nu red-black sweeps on level l with the single-cell kernel
+  void smooth_simple(int l, const T* rhs, Geo gr, int nu) {
     const Geo& G = H.geo[l];
     double h = 1.0 / (double)G.n;
     A h2 = (A)(h * h);
     int ce = cext(l);
+    // per half-sweep: read rhs and the other colour, write this colour
+    double bytes = 1.5 * sizeof(T) * c_cells(G);
     for (int it = 0; it < nu; ++it)
-      for (int col = 0; col < 2; ++col) {
-        hipLaunchKernelGGL((k_gs_half<T, A>), grid_for(cube(ce), nseg(l)), dim3(kBlock), 0, s,
-                           H.u[l], G, rhs, gr, col, h2, ce);
-        LAUNCH_CHECK("k_gs_half");
-      }
+      for (int col = 0; col < 2; ++col)
+        run("k_gs_half", bytes, grid_for(cube(ce), nseg(l)), dim3(kBlock), k_gs_half<T, A>,
+            H.u[l], G, rhs, gr, col, h2, ce);
   }
 
-  void coarse_solve(T* u0, const T* rhs0) {
-    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(kBlock), 0, s, u0, rhs0, P->Ainv,
-                       P->n0 * P->n0 * P->n0);
-    LAUNCH_CHECK("k_coarse_solve");
+  // one temporally blocked launch of NS half-sweeps with prologue PRO
+  template <int NS, int PRO>
+  void smooth_z(int l, const T* rhs, Geo gr, const T* c, Geo gc) {
+    // 64 x 32 tile: 16 wavefronts with 2 rows each (1024 threads)
+    constexpr int BYT = 16, RY = 2, TY = BYT * RY;
+    constexpr int SX = 64 - 2 * NS, SY = TY - 2 * NS;
+    const Geo& G = H.geo[l];
+    // every stored cell inside the domain is written, so the new copy is whole
+    int wext = cext(l) + 2 * G.ghost;
+    if (wext > G.n) wext = G.n;
+    if (PRO != PRO_LOAD && !c) throw hip_error("internal: null coarse increment");
+    SmoothArgs<T> a;
+    a.uin = H.u[l];
+    a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
+    H.u[l] = a.u;  // the written copy becomes current
+    a.gu = G;
+    a.rhs = rhs;
+    a.gr = gr;
+    a.c = c;
+    a.gc = gc;
+    double h = 1.0 / (double)G.n;
+    a.h2 = (T)(h * h);
+    a.ntx = (wext + SX - 1) / SX;
+    a.nty = (wext + SY - 1) / SY;
+    int ns = nseg(l);
+    long long bxy = (long long)a.ntx * a.nty * ns;
+    int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
+    // large levels keep chunks at least 2 NS deep (recomputed halo planes);
+    // small, L2-resident levels split finely to shorten the serial z march
+    int zmax = wext <= 64 ? (wext + 1) / 2 : wext / (2 * NS);
+    if (zmax < 1) zmax = 1;
+    if (ntz > zmax) ntz = zmax;
+    if (ntz < 1) ntz = 1;
+    a.zc = (wext + ntz - 1) / ntz;
+    a.ntz = (wext + a.zc - 1) / a.zc;
+    a.nxcd = ns > 1 ? 1 : P->nxcd;
+    int nt = a.ntx * a.nty * a.ntz;
+    int per = (nt + a.nxcd - 1) / a.nxcd;
+    double rd = PRO == PRO_CORRECT ? 1.125 : 1.0;
+    double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
+    run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>",
+        bytes, dim3(per * a.nxcd, ns), dim3(64 * BYT), k_smooth_z<T, NS, PRO, BYT, RY, kPrefetch<NS>>,
+        a);
+  }
+
+  template <int PRO>
+  void smooth_z_ns(int ns, int l, const T* rhs, Geo gr, const T* c, Geo gc) {
+    if (ns == 2) smooth_z<2, PRO>(l, rhs, gr, c, gc);
+    else smooth_z<4, PRO>(l, rhs, gr, c, gc);
+  }
+
+  // does a segment's whole storage box fit the box-resident smoother?
+  bool box_fits(int l) const {
+    const Geo& G = H.geo[l];
+    if (!G.ghost) return false;
+    long long ce = cext(l);
+    long long pairs = (ce + 1) / 2 * ce * ce;
+    return cube(G.m) * (long long)sizeof(T) <= P->lds_max && pairs <= kBoxSlots * kBoxThreads;
+  }
+
+  template <int PRO>
+  void smooth_box_pro(int l, const T* rhs, Geo gr, int nu, const T* d, Geo gc) {
+    const Geo& G = H.geo[l];
+    size_t shm = (size_t)cube(G.m) * sizeof(T);
+    static bool attr_set = false;  // once per instantiation: allow the device maximum
+    if (!dry && !attr_set) {
+      hipcheck(hipFuncSetAttribute((const void*)k_smooth_box<T, PRO>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max),
+               "hipFuncSetAttribute");
+      attr_set = true;
+    }
+    BoxArgs<T> a;
+    a.u = H.u[l];
+    a.gu = G;
+    a.rhs = rhs;
+    a.gr = gr;
+    a.d = PRO == PRO_CORRECT ? d : H.u[l];
+    a.gc = gc;
+    double h = 1.0 / (double)G.n;
+    a.h2 = (T)(h * h);
+    a.nu = nu;
+    double rd = PRO == PRO_CORRECT ? 1.125 : 1.0;
+    run_shm(PRO == PRO_CORRECT ? "k_smooth_box<correct>" : "k_smooth_box<load>",
+            sizeof(T) * (1.0 + rd) * c_cells(G) + sizeof(T) * nu * c_cells(G), dim3(nseg(l)),
+            dim3(kBoxThreads), shm, k_smooth_box<T, PRO>, a);
+  }
+
+  void smooth_box(int l, const T* rhs, Geo gr, int nu, int pro, const T* d, Geo gc) {
+    if (pro == PRO_CORRECT) smooth_box_pro<PRO_CORRECT>(l, rhs, gr, nu, d, gc);
+    else smooth_box_pro<PRO_LOAD>(l, rhs, gr, nu, d, gc);
+  }
+
+  // FMG interpolation onto the current copy of level l (streaming kernel)
+  void interp(int l) {
+    const Geo& G = H.geo[l];
+    const Geo& Gc = H.geo[l - 1];
+    int ce = G.ghost ? G.m : G.n;
+    int zc = ce < 32 ? ce : 32;
+    int ntz = (ce + zc - 1) / zc;
+    run("k_interp_z", sizeof(T) * 1.125 * st_cells(G),
+        grid_for((long long)ce * ce * ntz, nseg(l)), dim3(kBlock), k_interp_z<T>, H.u[l], G,
+        (const T*)H.u[l - 1], Gc, zc, ce);
+  }
+
+  // prologue (none, FMG interpolation from level l-1, or the coarse-grid
+  // correction from level l-1) followed by nu red-black sweeps on level l
+  void smooth(int l, const T* rhs, Geo gr, int nu, int pro = PRO_LOAD) {
+    lvl = l;
+    const Geo& G = H.geo[l];
+    const Geo& Gc = H.geo[l > 0 ? l - 1 : 0];
+    const T* d = l > 0 ? H.t[l - 1] : nullptr;
+    if (pro == PRO_INTERP) {
+      interp(l);
+      pro = PRO_LOAD;
+    }
+    if (pro == PRO_CORRECT) {
+      // d = w - t on the coarse level, over t
+      run("k_diff", 3.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nseg(l - 1)),
+          dim3(kBlock), k_diff<T>, (const T*)H.u[l - 1], H.t[l - 1], Gc);
+    }
+    int st = 2 * nu;
+    if (st > 0 && P->fused && box_fits(l)) {
+      smooth_box(l, rhs, gr, nu, pro, d, Gc);
+      return;
+    }
+    if (st == 0 || !P->fused) {
+      if (pro == PRO_CORRECT)
+        run("k_correct", sizeof(T) * 2.125 * st_cells(G), grid_for(cube(G.m), nseg(l)),
+            dim3(kBlock), k_correct<T>, H.u[l], G, d, Gc);
+      smooth_simple(l, rhs, gr, nu);
+      return;
+    }
+    bool first = true;
+    while (st > 0) {
+      int ns = st >= 4 ? 4 : st;
+      int pr = first ? pro : PRO_LOAD;
+      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, l, rhs, gr, d, Gc);
+      else smooth_z_ns<PRO_LOAD>(ns, l, rhs, gr, d, Gc);
+      st -= ns;
+      first = false;
+    }
+  }
+
+  // the persistent coarse-level kernel: FMG stages 0..top (mode 0) or one
+  // V-cycle on level top with right-hand side rt (mode 1)
+  void coarse(int top, int mode, const T* rt) {
+    lvl = top;
+    CoarseArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    double bytes = 0;
+    for (int l = 0; l <= top; ++l) {
+      a.u[l] = H.u[l];
+      a.t[l] = H.t[l];
+      a.r[l] = H.rhs[l];
+      a.f[l] = H.f[l];
+      a.n[l] = H.geo[l].n;
+      bytes += 4.0 * sizeof(T) * cube(a.n[l]);
+    }
+    a.Ainv = P->Ainv;
+    a.mm = P->n0 * P->n0 * P->n0;
+    a.top = top;
+    a.mode = mode;
+    a.rt = rt;
+    a.nu1 = P->nu1;
+    a.nu2 = P->nu2;
+    a.alpha = P->alpha;
+    run(mode == 0 ? "k_coarse<fmg>" : "k_coarse<vcycle>", bytes, dim3(1), dim3(kCoarseThreads),
+        k_coarse<T>, a);
+  }
+
+
+
+  // restriction of u and of the residual onto the coarse target cells, then
+  // the coarse right-hand side and t
+  void descend(int l, const T* rhs, Geo gr, int mode, int whole_f) {
+    lvl = l;
+    const Geo& G = H.geo[l];
+    const Geo& Gc = H.geo[l - 1];
+    int ns = nseg(l);
+    int ce = mode == 0 ? cext(l) / 2 : Gc.n / P->S;
+    double coarse = mode == 0 ? c_cells(G) / 8.0 : cube(Gc.n);
+    run("k_resid_restrict", sizeof(T) * (16.0 * coarse + 2.0 * coarse), grid_for(cube(ce), ns),
+        dim3(kBlock), k_resid_restrict<T>, (const T*)H.u[l], G, rhs, gr, H.u[l - 1],
+        H.rhs[l - 1], Gc, mode, ce);
+    int nsc = mode == 0 ? ns : 1;
+    run("k_coarse_rhs", 4.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nsc), dim3(kBlock),
+        k_coarse_rhs<T>, (const T*)H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, whole_f);
   }
 
   // FAS V-cycle on global level l with right-hand side rhs (Fig. 1)
-  void vcycle_global(int l, const T* rhs) {
-    if (l == 0) {
-      coarse_solve(H.u[0], rhs);
+  // presmoothed: S^nu1 has already been applied (fused with the FMG step)
+  void vcycle_global(int l, const T* rhs, bool presmoothed = false) {
+    if (l <= P->Lc) {
+      coarse(l, 1, rhs);
       return;
     }
     const Geo& G = H.geo[l];
-    const Geo& Gc = H.geo[l - 1];
-    smooth(l, rhs, G, P->nu1);
-    hipLaunchKernelGGL((k_resid_restrict<T>), grid_for(cube(G.n / 2), 1), dim3(kBlock), 0, s,
-                       H.u[l], G, rhs, G, H.u[l - 1], H.rhs[l - 1], Gc, 0, G.n / 2);
-    LAUNCH_CHECK("k_resid_restrict");
-    hipLaunchKernelGGL((k_coarse_rhs<T>), grid_for(cube(Gc.m), 1), dim3(kBlock), 0, s,
-                       H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, 1);
-    LAUNCH_CHECK("k_coarse_rhs");
+    if (!presmoothed) smooth(l, rhs, G, P->nu1);
+    descend(l, rhs, G, 0, 1);
     vcycle_global(l - 1, H.rhs[l - 1]);
-    hipLaunchKernelGGL((k_correct<T>), grid_for(cube(G.m), 1), dim3(kBlock), 0, s, H.u[l], G,
-                       H.u[l - 1], H.t[l - 1], Gc);
-    LAUNCH_CHECK("k_correct");
-    smooth(l, rhs, G, P->nu2);
+    smooth(l, rhs, G, P->nu2, PRO_CORRECT);
   }
 
   // SR V-cycle on segment level l inside the FMG stage whose top level is top
   // (Fig. 6); the top level's rhs is the global f_top read over C
-  void vcycle_sr(int l, int top) {
+  void vcycle_sr(int l, int top, bool presmoothed = false) {
     const Geo& G = H.geo[l];
-    const Geo& Gc = H.geo[l - 1];
     const T* rhs = (l == top) ? H.f[l] : H.rhs[l];
     Geo gr = (l == top) ? global_geo(G.n) : G;
-    int ns = nseg(l);
-    smooth(l, rhs, gr, P->nu1);
+    if (!presmoothed) smooth(l, rhs, gr, P->nu1);
     if (l - 1 > P->T) {
-      int ce = cext(l) / 2;
-      hipLaunchKernelGGL((k_resid_restrict<T>), grid_for(cube(ce), ns), dim3(kBlock), 0, s,
-                         H.u[l], G, rhs, gr, H.u[l - 1], H.rhs[l - 1], Gc, 0, ce);
-      LAUNCH_CHECK("k_resid_restrict");
-      hipLaunchKernelGGL((k_coarse_rhs<T>), grid_for(cube(Gc.m), ns), dim3(kBlock), 0, s,
-                         H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, 0);
-      LAUNCH_CHECK("k_coarse_rhs");
+      descend(l, rhs, gr, 0, 0);
       vcycle_sr(l - 1, top);
     } else {
-      int e = Gc.n / P->S;
-      hipLaunchKernelGGL((k_resid_restrict<T>), grid_for(cube(e), ns), dim3(kBlock), 0, s,
-                         H.u[l], G, rhs, gr, H.u[l - 1], H.rhs[l - 1], Gc, 1, e);
-      LAUNCH_CHECK("k_resid_restrict");
-      hipLaunchKernelGGL((k_coarse_rhs<T>), grid_for(cube(Gc.m), 1), dim3(kBlock), 0, s,
-                         H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, 1);
-      LAUNCH_CHECK("k_coarse_rhs");
+      descend(l, rhs, gr, 1, 1);  // owner-computes transition restriction
       vcycle_global(l - 1, H.rhs[l - 1]);
     }
-    hipLaunchKernelGGL((k_correct<T>), grid_for(cube(G.m), ns), dim3(kBlock), 0, s, H.u[l], G,
-                       H.u[l - 1], H.t[l - 1], Gc);
-    LAUNCH_CHECK("k_correct");
-    smooth(l, rhs, gr, P->nu2);
+    smooth(l, rhs, gr, P->nu2, PRO_CORRECT);
   }
 
   // one FMG solve: ftop is the finest right-hand side (global N^3 of T);
@@ -320,31 +613,30 @@ struct Exec {
   void fmg(const T* ftop, double* out, int acc) {
     int L = P->L;
     H.f[L - 1] = const_cast<T*>(ftop);
+    for (int l = 0; l < L; ++l) H.u[l] = H.ua[l];
     for (int l = L - 1; l > 0; --l) {
       int n = P->N >> (L - 1 - l);
-      hipLaunchKernelGGL((k_restrict_global<T, T>), grid_for(cube(n / 2), 1), dim3(kBlock), 0, s,
-                         H.f[l], n, H.f[l - 1]);
-      LAUNCH_CHECK("k_restrict_global");
+      lvl = l;
+      run("k_restrict_global", sizeof(T) * 1.125 * cube(n), grid_for(cube(n / 2), 1),
+          dim3(kBlock), k_restrict_global<T, T>, (const T*)H.f[l], n, H.f[l - 1]);
     }
-    coarse_solve(H.u[0], H.f[0]);
-    for (int l = 1; l < L; ++l) {
+    // FMG stages on the coarse global levels in one launch
+    coarse(P->Lc, 0, nullptr);
+    for (int l = P->Lc + 1; l < L; ++l) {
       const Geo& G = H.geo[l];
-      const Geo& Gc = H.geo[l - 1];
-      int ns = nseg(l);
-      hipLaunchKernelGGL((k_interp<T>), grid_for(cube(G.m), ns), dim3(kBlock), 0, s, H.u[l], G,
-                         H.u[l - 1], Gc);
-      LAUNCH_CHECK("k_interp");
-      smooth(l, H.f[l], global_geo(G.n), P->alpha);
+      // Pi, S^alpha and the V-cycle's S^nu1 form one fused pass
+      smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP);
       if (l <= P->T)
-        vcycle_global(l, H.f[l]);
+        vcycle_global(l, H.f[l], true);
       else
-        vcycle_sr(l, l);
+        vcycle_sr(l, l, true);
     }
     if (P->K > 0) {
       const Geo& G = H.geo[L - 1];
-      hipLaunchKernelGGL((k_gather<T>), grid_for(cube(G.g), nseg(L - 1)), dim3(kBlock), 0, s, out,
-                         H.u[L - 1], G, acc);
-      LAUNCH_CHECK("k_gather");
+      lvl = L - 1;
+      run("k_gather", (sizeof(T) + 8.0 + (acc ? 8.0 : 0.0)) * cube(P->N),
+          grid_for(cube(G.g), nseg(L - 1)), dim3(kBlock), k_gather<T>, out, (const T*)H.u[L - 1],
+          G, acc);
     }
   }
 };
@@ -354,22 +646,30 @@ static void execute(fmg_plan* P, const double* f, double* u, hipStream_t s) {
   long long cnt = cube(N);
   if (P->precision == FMG_FP64) {
     Exec<double> E{P, P->h64, s};
-    if (P->K == 0) P->h64.u[L - 1] = u;
+    E.dry = P->virt;
+    if (P->K == 0) {
+      // one copy of the finest level is the caller's u: start from the copy
+      // that makes the last smoothing pass write into u
+      double* ws = P->ws_finest;
+      P->h64.ua[L - 1] = P->finest_odd ? ws : u;
+      P->h64.ub[L - 1] = P->finest_odd ? u : ws;
+    }
+    if (!P->h64.ua[L - 1]) throw hip_error("internal: finest level has no storage");
     E.fmg(f, u, 0);
     return;
   }
   // mixed precision: u = FMG32(f); then refine times u += FMG32(f - L u)
   Exec<float> E{P, P->h32, s};
+  E.dry = P->virt;
   for (int it = 0; it <= P->refine; ++it) {
-    hipLaunchKernelGGL(k_resid64_to32, grid_for(cnt, 1), dim3(kBlock), 0, s, f,
-                       it == 0 ? (const double*)nullptr : (const double*)u, N, P->r32);
-    LAUNCH_CHECK("k_resid64_to32");
+    E.lvl = -1;
+    E.run("k_resid64_to32", (it ? 20.0 : 12.0) * cnt, grid_for(cnt, 1), dim3(kBlock),
+          k_resid64_to32, f, (const double*)u, (int)(it > 0), N, P->r32);
     E.fmg(P->r32, u, it > 0);
-    if (P->K == 0) {
-      hipLaunchKernelGGL((k_update64<float>), grid_for(cnt, 1), dim3(kBlock), 0, s, u,
-                         P->h32.u[L - 1], cnt, it > 0);
-      LAUNCH_CHECK("k_update64");
-    }
+    E.lvl = -1;
+    if (P->K == 0)
+      E.run("k_update64", (it ? 20.0 : 12.0) * cnt, grid_for(cnt, 1), dim3(kBlock),
+            k_update64<float>, u, (const float*)P->h32.u[L - 1], cnt, (int)(it > 0));
   }
 }
 
@@ -377,6 +677,84 @@ static void release(fmg_plan* P) {
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   delete P;
+}
+
+// Fill a plan: geometry, workspace (device memory, or virtual addresses for
+// the schedule model) and the FP64 coarsest-level inverse.
+static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt, fmg_plan** out) {
+  fmg_plan* P = new (std::nothrow) fmg_plan();
+  if (!P) return fail(FMG_ENOMEM, "host allocation failed");
+  P->virt = virt;
+  P->lds_max = 160 * 1024;
+  if (!virt) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)
+      P->lds_max = v;
+    else
+      (void)hipGetLastError();
+  }
+  P->N = N;
+  P->L = p->levels;
+  P->K = p->sr_levels;
+  P->T = P->L - 1 - P->K;
+  P->S = P->K > 0 ? p->segments_per_dim : 1;
+  P->n0 = N >> (P->L - 1);
+  P->device = device;
+  P->nu1 = p->nu_pre;
+  P->nu2 = p->nu_post;
+  P->alpha = p->alpha;
+  P->precision = p->precision;
+  P->refine = p->refine_iters;
+  P->J.assign(P->L, 0);
+  for (int l = P->T + 1; l < P->L; ++l) P->J[l] = p->buffer_schedule[P->L - 1 - l];
+  // coarse global levels: edge up to 16, at most the transition level
+  P->Lc = 0;
+  while (P->Lc + 1 <= P->T && (N >> (P->L - 2 - P->Lc)) <= 16 && P->Lc + 1 < kCoarseMaxLevels)
+    ++P->Lc;
+  std::vector<double> inv;
+  if (!coarse_inverse(P->n0, inv)) {
+    delete P;
+    return fail(FMG_EINVAL, "singular coarsest matrix");
+  }
+  try {
+    P->Ainv = (double*)dalloc(P, sizeof(double) * inv.size());
+    if (P->precision == FMG_FP64) {
+      build_hier(P, P->h64, true);
+      if (P->K == 0) {
+        // dry walk of the schedule: which copy holds the finest level last?
+        // (a one-level hierarchy is never smoothed and has no second copy)
+        P->ws_finest = P->h64.ub[P->L - 1];
+        double* fake_u = (double*)(uintptr_t)(1ull << 41);
+        P->h64.ua[P->L - 1] = fake_u;  // stands for the caller's array
+        Exec<double> E{P, P->h64, nullptr};
+        E.dry = true;
+        E.fmg((const double*)(uintptr_t)(1ull << 40), fake_u, 0);
+        P->finest_odd = P->h64.u[P->L - 1] != fake_u;
+        P->h64.ua[P->L - 1] = nullptr;
+        P->model_launches = 0;
+        P->model_bytes = 0;
+      }
+    } else {
+      build_hier(P, P->h32, false);
+      P->r32 = (float*)dalloc(P, sizeof(float) * cube(N));
+    }
+    if (!virt) {
+      // cells outside the domain and past a clipped box are never read; the
+      // workspace still starts from zeros so every byte has a defined value
+      for (size_t i = 0; i < P->allocs.size(); ++i)
+        hipcheck(hipMemset(P->allocs[i], 0, P->sizes[i]), "hipMemset");
+      hipcheck(hipMemcpy(P->Ainv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice),
+               "hipMemcpy");
+    }
+  } catch (const std::bad_alloc&) {
+    release(P);
+    return fail(FMG_ENOMEM, "device allocation failed");
+  } catch (const hip_error& ex) {
+    release(P);
+    return fail(FMG_EHIP, ex.what());
+  }
+  *out = P;
+  return FMG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -403,49 +781,34 @@ int32_t fmg_plan_create(int32_t N, const fmg_params* p, int32_t device, fmg_plan
     return fail(FMG_EINVAL, "invalid device");
   }
   if (hipSetDevice(device) != hipSuccess) return fail(FMG_EHIP, "hipSetDevice failed");
-  fmg_plan* P = new (std::nothrow) fmg_plan();
-  if (!P) return fail(FMG_ENOMEM, "host allocation failed");
-  P->N = N;
-  P->L = p->levels;
-  P->K = p->sr_levels;
-  P->T = P->L - 1 - P->K;
-  P->S = P->K > 0 ? p->segments_per_dim : 1;
-  P->n0 = N >> (P->L - 1);
-  P->device = device;
-  P->nu1 = p->nu_pre;
-  P->nu2 = p->nu_post;
-  P->alpha = p->alpha;
-  P->precision = p->precision;
-  P->refine = p->refine_iters;
-  P->J.assign(P->L, 0);
-  for (int l = P->T + 1; l < P->L; ++l) P->J[l] = p->buffer_schedule[P->L - 1 - l];
-  std::vector<double> inv;
-  if (!coarse_inverse(P->n0, inv)) {
-    delete P;
-    return fail(FMG_EINVAL, "singular coarsest matrix");
-  }
+  fmg_plan* P = nullptr;
+  int32_t st = build_plan(N, p, device, false, &P);
+  if (st == FMG_OK) *out = P;
+  return st;
+}
+
+int32_t fmg_schedule_model(int32_t N, const fmg_params* p, fmg_schedule_stat* out) {
+  if (!out) return fail(FMG_EINVAL, "out is NULL");
+  std::string e = check(N, p);
+  if (!e.empty()) return fail(FMG_EINVAL, e);
+  fmg_plan* P = nullptr;
+  int32_t st = build_plan(N, p, 0, true, &P);
+  if (st != FMG_OK) return st;
   try {
-    if (P->precision == FMG_FP64) {
-      build_hier(P, P->h64, true);
-    } else {
-      build_hier(P, P->h32, false);
-      P->r32 = (float*)dalloc(P, sizeof(float) * cube(N));
-    }
-    P->Ainv = (double*)dalloc(P, sizeof(double) * inv.size());
-    // cells outside the domain and past a clipped box are never read; the
-    // workspace still starts from zeros so every byte has a defined value
-    for (size_t i = 0; i < P->allocs.size(); ++i)
-      hipcheck(hipMemset(P->allocs[i], 0, P->sizes[i]), "hipMemset");
-    hipcheck(hipMemcpy(P->Ainv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice),
-             "hipMemcpy");
-  } catch (const std::bad_alloc&) {
-    release(P);
-    return fail(FMG_ENOMEM, "device allocation failed");
+    // two fake, distinct caller arrays
+    const double* f = (const double*)(uintptr_t)(1ull << 40);
+    double* u = (double*)(uintptr_t)(1ull << 41);
+    P->model_launches = 0;
+    P->model_bytes = 0;
+    execute(P, f, u, nullptr);
+    out->launches = P->model_launches;
+    out->bytes = P->model_bytes;
+    out->workspace_bytes = P->bytes;
   } catch (const hip_error& ex) {
-    release(P);
+    delete P;
     return fail(FMG_EHIP, ex.what());
   }
-  *out = P;
+  delete P;
   return FMG_OK;
 }
 
@@ -488,6 +851,55 @@ int32_t fmg_solve(const double* f, int32_t N, const fmg_params* p, double* u, vo
 
 int64_t fmg_plan_workspace_bytes(const fmg_plan* P) { return P ? P->bytes : 0; }
 
+int32_t fmg_plan_profile(fmg_plan* P, int32_t enable) {
+  if (!P) return fail(FMG_EINVAL, "plan is NULL");
+  try {
+    if (!P->prof.recs.empty()) {
+      hipcheck(hipEventSynchronize(P->prof.recs.back().b), "hipEventSynchronize");
+      P->prof.recycle();
+    }
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  P->prof.on = enable != 0;
+  return FMG_OK;
+}
+
+int32_t fmg_plan_profile_read(fmg_plan* P, fmg_kernel_stat* out, int32_t cap, int32_t* count) {
+  if (!P || !count || (cap > 0 && !out)) return fail(FMG_EINVAL, "bad arguments");
+  std::vector<fmg_kernel_stat> agg;
+  try {
+    if (!P->prof.recs.empty())
+      hipcheck(hipEventSynchronize(P->prof.recs.back().b), "hipEventSynchronize");
+    for (auto& r : P->prof.recs) {
+      float ms = 0.f;
+      hipcheck(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+      char key[64];
+      if (r.level >= 0)
+        std::snprintf(key, sizeof key, "%s@%d", r.name, r.level);
+      else
+        std::snprintf(key, sizeof key, "%s", r.name);
+      size_t i = 0;
+      while (i < agg.size() && std::strcmp(agg[i].name, key) != 0) ++i;
+      if (i == agg.size()) {
+        fmg_kernel_stat z;
+        std::memset(&z, 0, sizeof z);
+        std::snprintf(z.name, sizeof z.name, "%s", key);
+        agg.push_back(z);
+      }
+      agg[i].launches += 1;
+      agg[i].total_ms += ms;
+      agg[i].bytes += r.bytes;
+    }
+    P->prof.recycle();
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  *count = (int32_t)agg.size();
+  for (int32_t i = 0; i < cap && i < (int32_t)agg.size(); ++i) out[i] = agg[i];
+  return FMG_OK;
+}
+
 int32_t fmg_op_apply(const double* u, int32_t n, double* out, void* stream) {
   if (!u || !out || n < 1) return fail(FMG_EINVAL, "bad arguments");
   Geo G = global_geo(n);
@@ -499,14 +911,35 @@ int32_t fmg_op_apply(const double* u, int32_t n, double* out, void* stream) {
 
 int32_t fmg_op_smooth(double* u, const double* rhs, int32_t n, int32_t nu, void* stream) {
   if (!u || !rhs || n < 1 || nu < 0) return fail(FMG_EINVAL, "bad arguments");
-  Geo G = global_geo(n);
-  double h = 1.0 / (double)n;
-  for (int it = 0; it < nu; ++it)
-    for (int col = 0; col < 2; ++col)
-      hipLaunchKernelGGL((k_gs_half<double, double>), grid_for(cube(n), 1), dim3(kBlock), 0,
-                         (hipStream_t)stream, u, G, rhs, G, col, h * h, n);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? FMG_OK : fail(FMG_EHIP, hipGetErrorString(e));
+  // a one-level plan over the caller's arrays: the smoother runs exactly as
+  // inside a solve; its second copy of u is a temporary buffer
+  hipStream_t st = (hipStream_t)stream;
+  double* tmp = nullptr;
+  size_t bytes = sizeof(double) * (size_t)cube(n);
+  if (hipMalloc(&tmp, bytes) != hipSuccess) return fail(FMG_ENOMEM, "hipMalloc failed");
+  int32_t ret = FMG_OK;
+  {
+    fmg_plan P;
+    P.N = n;
+    P.L = 1;
+    P.T = 0;
+    P.h64.geo.assign(1, global_geo(n));
+    P.h64.ua.assign(1, u);
+    P.h64.ub.assign(1, tmp);
+    P.h64.u.assign(1, u);
+    P.h64.t.assign(1, nullptr);
+    try {
+      Exec<double> E{&P, P.h64, st};
+      E.smooth(0, rhs, global_geo(n), nu);
+      if (P.h64.u[0] != u)
+        hipcheck(hipMemcpyAsync(u, tmp, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+      hipcheck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    } catch (const hip_error& ex) {
+      ret = fail(FMG_EHIP, ex.what());
+    }
+  }
+  (void)hipFree(tmp);
+  return ret;
 }
 
 int32_t fmg_op_restrict(const double* fine, int32_t n, double* coarse, void* stream) {
@@ -520,8 +953,9 @@ int32_t fmg_op_restrict(const double* fine, int32_t n, double* coarse, void* str
 int32_t fmg_op_interp(const double* coarse, int32_t n, double* fine, void* stream) {
   if (!fine || !coarse || n < 1) return fail(FMG_EINVAL, "bad arguments");
   Geo Gf = global_geo(2 * n), Gc = global_geo(n);
-  hipLaunchKernelGGL((k_interp<double>), grid_for(cube(2 * n), 1), dim3(kBlock), 0,
-                     (hipStream_t)stream, fine, Gf, coarse, Gc);
+  int ce = 2 * n, zc = ce < 32 ? ce : 32, ntz = (ce + zc - 1) / zc;
+  hipLaunchKernelGGL((k_interp_z<double>), grid_for((long long)ce * ce * ntz, 1), dim3(kBlock), 0,
+                     (hipStream_t)stream, fine, Gf, coarse, Gc, zc, ce);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FMG_OK : fail(FMG_EHIP, hipGetErrorString(e));
 }

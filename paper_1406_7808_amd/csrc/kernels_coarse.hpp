@@ -1,0 +1,177 @@
+// kernels_coarse.hpp -- the coarse global levels in one persistent workgroup.
+//
+// Levels whose grids are small (up to 16^3 cells) are latency bound: a kernel
+// launch per operator costs more than the work.  k_coarse runs every
+// operator of these levels inside one workgroup, with a block barrier between
+// phases, on the same level arrays the other kernels use (they stay resident
+// in L2).  It performs either
+//   mode 0: FMG stages 0..top (Fig. 2 of the paper): u_0 = L_0^-1 f_0, then
+//           per level Pi, S^alpha and one FAS V-cycle with rhs f_l, or
+//   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt.
+// Every phase applies exactly the per-cell arithmetic of the single-cell
+// kernels; updates of one colour are independent, so the in-place half-sweep
+// is an exact Gauss-Seidel half-sweep.
+#pragma once
+#include "grid.hpp"
+#include "kernels_simple.hpp"
+
+namespace fmg {
+
+constexpr int kCoarseMaxLevels = 8;
+constexpr int kCoarseThreads = 1024;
+
+template <class T>
+struct CoarseArgs {
+  T* u[kCoarseMaxLevels];
+  T* t[kCoarseMaxLevels];
+  T* r[kCoarseMaxLevels];        // rhs of the V-cycle on each level below top
+  const T* f[kCoarseMaxLevels];  // FMG right-hand sides
+  int n[kCoarseMaxLevels];
+  const double* Ainv;
+  int mm;
+  int top;
+  int mode;
+  const T* rt;  // mode 1: rhs of level top
+  int nu1, nu2, alpha;
+};
+
+template <class T>
+__device__ void blk_gs(T* u, const T* rhs, int n, int nu) {
+  const Geo G = global_geo(n);
+  const Box B = seg_box(G, 0);
+  const int cnt = n * n * n, n2 = n * n;
+  const double h = 1.0 / (double)n;
+  const T h2 = (T)(h * h);
+  for (int it = 0; it < nu; ++it)
+    for (int col = 0; col < 2; ++col) {
+      for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+        int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
+        if (((x + y + z) & 1) != col) continue;
+        int nb;
+        T s = nb_sum<T, T>(u, G, B, x, y, z, nb);
+        u[c] = (s - h2 * rhs[c]) / (T)(6 + nb);
+      }
+      __syncthreads();
+    }
+}
+
+// uc = R u, rc = R (rhs - L u) on every coarse cell; then t = uc and
+// rc = rc + L_H uc (FAS right-hand side, Eq. 4)
+template <class T>
+__device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc) {
+  const Geo G = global_geo(n);
+  const Box B = seg_box(G, 0);
+  const int nc = n / 2, nc2 = nc * nc;
+  const int cc = nc * nc2;
+  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
+    int K = c / nc2, J = (c - K * nc2) / nc, I = c - K * nc2 - J * nc;
+    double su = 0.0, sr = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+          int id = (k * n + j) * n + i;
+          su += (double)u[id];
+          sr += (double)rhs[id] - apply_L<T, double>(u, G, B, i, j, k);
+        }
+    uc[c] = (T)(su / 8.0);
+    rc[c] = (T)(sr / 8.0);
+  }
+  __syncthreads();
+  const Geo Gc = global_geo(nc);
+  const Box Bc = seg_box(Gc, 0);
+  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
+    int K = c / nc2, J = (c - K * nc2) / nc, I = c - K * nc2 - J * nc;
+    tc[c] = uc[c];
+    rc[c] = (T)((double)rc[c] + apply_L<T, double>(uc, Gc, Bc, I, J, K));
+  }
+  __syncthreads();
+}
+
+// u += P(w - t): the increment is formed per fine cell from the coarse pair
+template <class T>
+__device__ void blk_correct(T* u, int n, const T* w, const T* t) {
+  const int nc = n / 2, n2 = n * n;
+  const int cnt = n * n2;
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
+    int pc = ((z >> 1) * nc + (y >> 1)) * nc + (x >> 1);
+    u[c] = (T)(u[c] + (w[pc] - t[pc]));
+  }
+  __syncthreads();
+}
+
+template <class T>
+__device__ void blk_interp(T* u, int n, const T* c) {
+  const Geo G = global_geo(n), Gc = global_geo(n / 2);
+  const Box Bc = seg_box(Gc, 0);
+  const int n2 = n * n, cnt = n * n2;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
+    int f[3] = {x, y, z};
+    int nc = n / 2, p[3], r[3];
+    for (int d = 0; d < 3; ++d) {
+      p[d] = f[d] >> 1;
+      r[d] = (f[d] & 1) ? p[d] + 1 : p[d] - 1;
+    }
+    T s = 0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          int id3[3] = {cx ? r[0] : p[0], cy ? r[1] : p[1], cz ? r[2] : p[2]};
+          T w = (T)((cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75));
+          T sign = 1;
+          for (int d = 0; d < 3; ++d) {
+            if (id3[d] < 0) { id3[d] = -1 - id3[d]; sign = -sign; }
+            else if (id3[d] >= nc) { id3[d] = 2 * nc - 1 - id3[d]; sign = -sign; }
+          }
+          s += w * sign * c[at(Gc, Bc, id3[0], id3[1], id3[2])];
+        }
+    u[i] = s;
+  }
+  (void)G;
+  __syncthreads();
+}
+
+template <class T>
+__device__ void blk_coarse_solve(T* u0, const T* rhs0, const double* Ainv, int mm) {
+  for (int r = threadIdx.x; r < mm; r += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < mm; ++c) s += Ainv[r * mm + c] * (double)rhs0[c];
+    u0[r] = (T)s;
+  }
+  __syncthreads();
+}
+
+// FAS V-cycle from level top with right-hand side rt, down to the exact
+// coarsest solve and back up
+template <class T>
+__device__ void blk_vcycle(const CoarseArgs<T>& a, int top, const T* rt) {
+  for (int l = top; l >= 1; --l) {
+    const T* rhs = (l == top) ? rt : a.r[l];
+    blk_gs(a.u[l], rhs, a.n[l], a.nu1);
+    blk_descend(a.u[l], rhs, a.n[l], a.u[l - 1], a.r[l - 1], a.t[l - 1]);
+  }
+  blk_coarse_solve(a.u[0], top == 0 ? rt : a.r[0], a.Ainv, a.mm);
+  for (int l = 1; l <= top; ++l) {
+    const T* rhs = (l == top) ? rt : a.r[l];
+    blk_correct(a.u[l], a.n[l], a.u[l - 1], a.t[l - 1]);
+    blk_gs(a.u[l], rhs, a.n[l], a.nu2);
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> a) {
+  if (a.mode == 1) {
+    blk_vcycle(a, a.top, a.rt);
+    return;
+  }
+  blk_coarse_solve(a.u[0], a.f[0], a.Ainv, a.mm);
+  for (int l = 1; l <= a.top; ++l) {
+    blk_interp(a.u[l], a.n[l], a.u[l - 1]);
+    blk_gs(a.u[l], a.f[l], a.n[l], a.alpha);
+    blk_vcycle(a, l, a.f[l]);
+  }
+}
+
+}  // namespace fmg

@@ -1,0 +1,395 @@
+// kernels_fused.hpp -- temporally blocked red-black Gauss-Seidel smoother and
+// a streaming FMG interpolation.
+//
+// k_smooth_z applies NS half-sweeps (NS/2 red-black sweeps, red first) to the
+// compute region C of every segment of a level in one pass over HBM:
+//
+//  * a workgroup owns an xy tile of 64 x TY columns (TY = BYT * RY: BYT
+//    wavefronts, RY rows per thread) and marches through a z chunk;
+//  * the planes of the z window live in registers: at step p the thread holds
+//    plane p, and half-sweep s (s = 1..NS) updates plane p - s, so the NS
+//    half-sweeps run as a wavefront in z;
+//  * loads run PF planes ahead of use through a ring of registers (the step
+//    loop is unrolled PF times), so memory latency overlaps the LDS work of
+//    the steps in between; loads are issued unconditionally so the compiler
+//    can count them;
+//  * x and y neighbours are exchanged through LDS (one barrier per stage);
+//  * tiles overlap by NS cells in x and y and a chunk starts NS planes early:
+//    the halo is recomputed instead of exchanged, so after NS stages the inner
+//    tile and chunk are exact;
+//  * u is read from one copy and written to the other: neighbouring tiles
+//    overlap, so an in-place update would let a tile read halo cells that its
+//    neighbour has already advanced.  Every stored cell inside the domain is
+//    written (GSR ghosts unchanged), so the written copy is complete;
+//  * the load stage is either u itself or u + P(d) with d = w - t on the
+//    coarse level, the coarse-grid correction of Fig. 1 and Fig. 6 of the
+//    paper (piecewise-constant prolongation), applied on C and the GSR ghosts
+//    alike.
+//
+// A cell of C gets the same point update as in the single-cell kernel,
+// u_c = (sum of in-domain neighbours - h^2 rhs_c) / (6 + b_c), with the
+// division replaced by a product with the precomputed 1 / (6 + b_c).
+#pragma once
+#include "grid.hpp"
+#include "kernels_simple.hpp"
+
+namespace fmg {
+
+enum { PRO_LOAD = 0, PRO_INTERP = 1, PRO_CORRECT = 2 };
+
+template <class T>
+struct SmoothArgs {
+  const T* uin;  // current u (read)
+  T* u;          // the other copy of u (written)
+  Geo gu;
+  const T* rhs;
+  Geo gr;
+  const T* c;   // coarse d = w - t (correct)
+  Geo gc;
+  T h2;
+  int ntx, nty, ntz;  // tiles per dimension of the write region
+  int zc;             // planes per z chunk
+  int nxcd;           // blocks are dealt to this many L2 domains in turn
+};
+
+template <class T, int NS, int PRO, int BYT, int RY, int PF>
+__global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
+  constexpr int TX = 64, TY = BYT * RY, H = NS;
+  constexpr int SX = TX - 2 * H, SY = TY - 2 * H;
+  static_assert(SX > 0 && SY > 0, "tile too small for the number of stages");
+  static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT, "interpolation has its own kernel");
+  __shared__ T lds[2][TY][TX + 1];  // neighbour exchange, one buffer per stage parity
+
+  const Geo gu = a.gu;
+  const int q = blockIdx.y;
+  const Box B = seg_box(gu, q);
+  const int n = gu.n;
+  // blocks are dealt round-robin to the L2 domains: give each domain a
+  // contiguous range of tiles so neighbouring tiles share an L2
+  int tid = blockIdx.x;
+  {
+    int nt = a.ntx * a.nty * a.ntz;
+    int per = (nt + a.nxcd - 1) / a.nxcd;
+    int t2 = (tid % a.nxcd) * per + tid / a.nxcd;
+    if (t2 >= nt) return;
+    tid = t2;
+  }
+  const int ti = tid % a.ntx, tj = (tid / a.ntx) % a.nty, tk = tid / (a.ntx * a.nty);
+
+  // write region: every stored cell inside the domain
+  int wlo[3], whi[3];
+  for (int d = 0; d < 3; ++d) {
+    wlo[d] = B.o[d] < 0 ? 0 : B.o[d];
+    whi[d] = B.o[d] + gu.m > n ? n : B.o[d] + gu.m;
+  }
+  const int ox = wlo[0] + ti * SX, oy = wlo[1] + tj * SY, oz = wlo[2] + tk * a.zc;
+  if (ox >= whi[0] || oy >= whi[1] || oz >= whi[2]) return;
+  const int oz1 = oz + a.zc < whi[2] ? oz + a.zc : whi[2];
+  const long long mm = (long long)gu.m * gu.m;
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+
+  // steps p0..p1, padded to a multiple of PF: the padding steps only touch
+  // planes past the chunk, whose results are never stored
+  const int p0 = oz - NS, p1 = oz1 - 1 + NS;
+  const int nsteps = ((p1 - p0 + 1) + PF - 1) / PF * PF;
+
+  const int x = ox - H + lane;
+  const bool xs = x >= wlo[0] && x < whi[0];
+  const bool xc = x >= B.a[0] && x < B.b[0];
+  const int nbx = (x == 0) + (x == n - 1);
+
+  const Box Br = seg_box(a.gr, q);
+  const Box Bc = seg_box(a.gc, q);
+  T* __restrict__ wb = a.u + B.base;
+  const T* __restrict__ ub = a.uin + B.base;
+  const T* __restrict__ rb = a.rhs + Br.base;
+  const T* __restrict__ cd = PRO == PRO_CORRECT ? a.c + Bc.base : nullptr;
+  const long long rmm = (long long)a.gr.m * a.gr.m;
+  const long long cmm = (long long)a.gc.m * a.gc.m;
+
+  T U[NS + 2][RY], F[NS + 1][RY];
+  T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY];  // ring of planes in flight
+  int ys[RY], uo[RY], ro[RY], co[RY];
+  unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge
+  T inv[RY];        // 1 / (6 + b_c) away from the z walls
+  int nbxy[RY];     // boundary faces in x and y
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    int ly = wy + BYT * r;
+    int y = oy - H + ly;
+    ys[r] = y;
+    bool ysok = y >= wlo[1] && y < whi[1];
+    bool yc = y >= B.a[1] && y < B.b[1];
+    bool yo = ly >= H && ly < TY - H;
+    bool xo = lane >= H && lane < TX - H;
+    bool inner = lane > 0 && lane < TX - 1 && ly > 0 && ly < TY - 1;
+    ok[r] = (xs && ysok ? 1u : 0u) | (xc && yc ? 2u : 0u) | (xo && yo && xs && ysok ? 4u : 0u) |
+            (inner ? 8u : 0u);
+    uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
+    ro[r] = (y - Br.o[1]) * a.gr.m + (x - Br.o[0]);
+    co[r] = ((y >> 1) - Bc.o[1]) * a.gc.m + ((x >> 1) - Bc.o[0]);
+    nbxy[r] = nbx + (y == 0) + (y == n - 1);
+    inv[r] = (T)1 / (T)(6 + nbxy[r]);
+#pragma unroll
+    for (int j = 0; j < NS + 2; ++j) U[j][r] = 0;
+#pragma unroll
+    for (int j = 0; j < NS + 1; ++j) F[j][r] = 0;
+  }
+
+  // issue the loads of plane p into a ring slot (raw values, used PF steps
+  // later).  Every load is issued unconditionally -- lanes with nothing to
+  // read fetch the first element of the same array and their validity bit
+  // masks the value at use -- so loads in flight can be counted exactly.
+  unsigned Vu[PF], Vf[PF];
+  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], unsigned& vu, unsigned& vf) {
+    const bool zs = p >= wlo[2] && p < whi[2];
+    const bool zcin = p >= B.a[2] && p < B.b[2];
+    const long long pu = (long long)(p - B.o[2]) * mm;
+    const long long pr = (long long)(p - Br.o[2]) * rmm;
+    const long long pc = (long long)((p >> 1) - Bc.o[2]) * cmm;
+    vu = 0;
+    vf = 0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const bool v = zs && (ok[r] & 1u);
+      const bool w = v && zcin && (ok[r] & 2u);
+      vu |= (v ? 1u : 0u) << r;
+      vf |= (w ? 1u : 0u) << r;
+      qu[r] = ub[v ? pu + uo[r] : 0];
+      if (PRO == PRO_CORRECT) qd[r] = cd[v ? pc + co[r] : 0];
+      qf[r] = rb[w ? pr + ro[r] : 0];
+    }
+  };
+
+#pragma unroll
+  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Vu[k], Vf[k]);
+  for (int pb = p0; pb < p0 + nsteps; pb += PF) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int p = pb + k;
+#pragma unroll
+      for (int j = NS + 1; j > 0; --j)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) U[j][r] = U[j - 1][r];
+#pragma unroll
+      for (int j = NS; j > 0; --j)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const T v = PRO == PRO_CORRECT ? Qu[k][r] + Qd[k][r] : Qu[k][r];
+        U[0][r] = ((Vu[k] >> r) & 1u) ? v : (T)0;
+        F[0][r] = ((Vf[k] >> r) & 1u) ? Qf[k][r] : (T)0;
+      }
+      fetch(p + PF, Qu[k], Qf[k], Qd[k], Vu[k], Vf[k]);
+      // NS half-sweeps as a wavefront: stage s updates plane p - s
+#pragma unroll
+      for (int s = 1; s <= NS; ++s) {
+        const int zp = p - s;
+        const int col = (s - 1) & 1;
+        const int b = s & 1;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) lds[b][wy + BYT * r][lane] = U[s][r];
+        __syncthreads();
+        const bool zin = zp >= B.a[2] && zp < B.b[2];
+        const int nbz = (zp == 0) + (zp == n - 1);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          const int ly = wy + BYT * r;
+          const bool act = zin && ((ok[r] & 10u) == 10u) && (((x + ys[r] + zp) & 1) == col);
+          if (act) {
+            T sum = lds[b][ly][lane - 1] + lds[b][ly][lane + 1] + lds[b][ly - 1][lane] +
+                    lds[b][ly + 1][lane] + U[s - 1][r] + U[s + 1][r];
+            if (nbz == 0)  // uniform across the block
+              U[s][r] = (sum - a.h2 * F[s][r]) * inv[r];
+            else
+              U[s][r] = (sum - a.h2 * F[s][r]) * ((T)1 / (T)(6 + nbxy[r] + nbz));
+          }
+        }
+      }
+      // plane p - NS is final
+      const int zo = p - NS;
+      if (zo >= oz && zo < oz1) {
+        const long long pw = (long long)(zo - B.o[2]) * mm;
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+          if (ok[r] & 4u) wb[pw + uo[r]] = U[NS][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FMG interpolation Pi (Sec. 3.2): trilinear with odd reflection at the walls,
+// onto every stored cell inside the domain (C and GSR ghosts).  One thread
+// per fine column marches a z chunk.  Fine plane z uses the coarse planes lo
+// and lo + 1 with lo = floor((z - 1) / 2): child 2P takes 3/4 c(P) + 1/4
+// c(P-1), child 2P+1 takes 3/4 c(P) + 1/4 c(P+1).  The xy interpolation of a
+// coarse plane (4 loads) is kept while two consecutive fine planes use it, and
+// only the planes a fine plane needs are read (they lie in the coarse
+// segment's storage when the coarser buffer is at least half as wide).
+template <class T>
+__global__ void __launch_bounds__(256) k_interp_z(T* __restrict__ u, Geo gu,
+                                                  const T* __restrict__ c, Geo gc, int zc, int ce) {
+  const int q = blockIdx.y;
+  const Box B = seg_box(gu, q), Bc = seg_box(gc, q);
+  const int n = gu.n, nc = gc.n;
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = B.o[d] < 0 ? 0 : B.o[d];
+    hi[d] = B.o[d] + gu.m > n ? n : B.o[d] + gu.m;
+  }
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cx = (int)(t % ce);
+  t /= ce;
+  const int cy = (int)(t % ce);
+  const int kz = (int)(t / ce);
+  const int x = lo[0] + cx, y = lo[1] + cy, z0 = lo[2] + kz * zc;
+  if (x >= hi[0] || y >= hi[1] || z0 >= hi[2]) return;
+  const int z1 = z0 + zc < hi[2] ? z0 + zc : hi[2];
+
+  // xy stencil of this column: coarse columns (X0|X1, Y0|Y1) and weights
+  int X0 = x >> 1, Y0 = y >> 1;
+  int X1 = (x & 1) ? X0 + 1 : X0 - 1, Y1 = (y & 1) ? Y0 + 1 : Y0 - 1;
+  T sx = 1, sy = 1;
+  if (X1 < 0) { X1 = 0; sx = -1; }
+  if (X1 >= nc) { X1 = nc - 1; sx = -1; }
+  if (Y1 < 0) { Y1 = 0; sy = -1; }
+  if (Y1 >= nc) { Y1 = nc - 1; sy = -1; }
+  const T w00 = (T)0.5625, w10 = (T)0.1875 * sx, w01 = (T)0.1875 * sy, w11 = (T)0.0625 * sx * sy;
+  const T* __restrict__ cb = c + Bc.base;
+  const long long cmm = (long long)gc.m * gc.m;
+  const int o00 = (Y0 - Bc.o[1]) * gc.m + (X0 - Bc.o[0]);
+  const int o10 = (Y0 - Bc.o[1]) * gc.m + (X1 - Bc.o[0]);
+  const int o01 = (Y1 - Bc.o[1]) * gc.m + (X0 - Bc.o[0]);
+  const int o11 = (Y1 - Bc.o[1]) * gc.m + (X1 - Bc.o[0]);
+  // xy-interpolated coarse plane P, odd reflection outside [0, nc)
+  auto plane = [&](int P) -> T {
+    T sg = 1;
+    if (P < 0) { P = -1 - P; sg = -1; }
+    if (P >= nc) { P = 2 * nc - 1 - P; sg = -1; }
+    const long long pz = (long long)(P - Bc.o[2]) * cmm;
+    return sg * (w00 * cb[pz + o00] + w10 * cb[pz + o10] + w01 * cb[pz + o01] +
+                 w11 * cb[pz + o11]);
+  };
+  T* __restrict__ ucol = u + B.base + (long long)(y - B.o[1]) * gu.m + (x - B.o[0]);
+  const long long mm = (long long)gu.m * gu.m;
+  int lo_p = (z0 - 1) >> 1;
+  T clo = plane(lo_p), chi = plane(lo_p + 1);
+  for (int z = z0; z < z1; ++z) {
+    const int l = (z - 1) >> 1;
+    if (l != lo_p) {  // advance by one coarse plane
+      lo_p = l;
+      clo = chi;
+      chi = plane(l + 1);
+    }
+    T v = (z & 1) ? (T)0.75 * clo + (T)0.25 * chi : (T)0.75 * chi + (T)0.25 * clo;
+    ucol[(long long)(z - B.o[2]) * mm] = v;
+  }
+}
+
+}  // namespace fmg
+
+namespace fmg {
+
+// ---------------------------------------------------------------------------
+// Box-resident smoother for segment levels whose whole storage box fits in
+// LDS (Sec. 4 of the paper: a segment is processed on its own, with frozen
+// ghosts).  One workgroup per segment loads the box (u, or u + P(d) for the
+// coarse-grid correction), applies nu red-black sweeps in LDS with a barrier
+// between half-sweeps, and writes the box back in place (segments own their
+// storage, so no other workgroup reads it meanwhile).  Each thread owns fixed
+// pairs of x-adjacent cells, one of each colour, so every thread updates a
+// cell in every half-sweep.
+constexpr int kBoxThreads = 1024;
+constexpr int kBoxSlots = 8;  // cell pairs per thread
+
+template <class T>
+struct BoxArgs {
+  T* u;
+  Geo gu;
+  const T* rhs;
+  Geo gr;
+  const T* d;  // coarse increment (correct)
+  Geo gc;
+  T h2;
+  int nu;
+};
+
+template <class T, int PRO>
+__global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* bu = reinterpret_cast<T*>(smem_raw);
+  const Geo gu = a.gu;
+  const int q = blockIdx.x, n = gu.n, m = gu.m, m2 = m * m, mc = m * m2;
+  const Box B = seg_box(gu, q), Br = seg_box(a.gr, q), Bc = seg_box(a.gc, q);
+  T* __restrict__ ub = a.u + B.base;
+  const T* __restrict__ rb = a.rhs + Br.base;
+
+  for (int c = threadIdx.x; c < mc; c += blockDim.x) {
+    const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
+    const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
+    T v = 0;
+    if (in_dom(n, x, y, z)) {
+      v = ub[c];
+      if (PRO == PRO_CORRECT) v = v + a.d[at(a.gc, Bc, x >> 1, y >> 1, z >> 1)];
+    }
+    bu[c] = v;
+  }
+
+  // cell pairs of C: pair (xp, y, z) holds x = a0 + 2 xp and x + 1
+  const int cx = B.b[0] - B.a[0], cy = B.b[1] - B.a[1], cz = B.b[2] - B.a[2];
+  const int px = (cx + 1) / 2, np = px * cy * cz;
+  int li[kBoxSlots], gi[kBoxSlots];
+  unsigned fl[kBoxSlots];  // bit0 parity of the first cell, bit1 second cell exists,
+                           // bits 2-4 / 5-7 boundary faces of the first / second cell
+  int ns = 0;
+#pragma unroll
+  for (int t = 0; t < kBoxSlots; ++t) {
+    const int s = threadIdx.x + t * kBoxThreads;
+    li[t] = 0;
+    gi[t] = 0;
+    fl[t] = 0;
+    if (s < np) {
+      const int zz = s / (px * cy), yy = (s - zz * px * cy) / px, xp = s - zz * px * cy - yy * px;
+      const int x = B.a[0] + 2 * xp, y = B.a[1] + yy, z = B.a[2] + zz;
+      li[t] = ((z - B.o[2]) * m + (y - B.o[1])) * m + (x - B.o[0]);
+      gi[t] = (int)(((long long)(z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]));
+      const int byz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
+      const int nb0 = byz + (x == 0) + (x == n - 1);
+      const int nb1 = byz + (x + 1 == 0) + (x + 1 == n - 1);
+      fl[t] = ((x + y + z) & 1) | ((x + 1 < B.b[0]) ? 2u : 0u) | (nb0 << 2) | (nb1 << 5);
+      ns = t + 1;
+    }
+  }
+  __syncthreads();
+
+  for (int it = 0; it < a.nu; ++it)
+    for (int col = 0; col < 2; ++col) {
+#pragma unroll
+      for (int t = 0; t < kBoxSlots; ++t) {
+        if (t < ns) {
+          const int off = (fl[t] ^ col) & 1;  // which cell of the pair has colour col
+          if (!off || (fl[t] & 2u)) {
+            const int l = li[t] + off;
+            const T s = bu[l - 1] + bu[l + 1] + bu[l - m] + bu[l + m] + bu[l - m2] + bu[l + m2];
+            const int nb = off ? (fl[t] >> 5) & 7 : (fl[t] >> 2) & 7;
+            bu[l] = (s - a.h2 * rb[gi[t] + off]) / (T)(6 + nb);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+  // write back: the compute region, and the ghosts when the prologue changed them
+  for (int c = threadIdx.x; c < mc; c += blockDim.x) {
+    const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
+    const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
+    if (!in_dom(n, x, y, z)) continue;
+    const bool inC = x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1] && z >= B.a[2] &&
+                     z < B.b[2];
+    if (inC || PRO == PRO_CORRECT) ub[c] = bu[c];
+  }
+}
+
+}  // namespace fmg

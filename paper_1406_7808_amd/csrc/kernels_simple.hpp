@@ -152,10 +152,24 @@ __global__ void k_coarse_rhs(const T* __restrict__ uc, T* __restrict__ rc, T* __
   rc[id] = (T)(r + Lu);
 }
 
-// u += P(w - t) on C and the GSR ghosts (every stored cell inside the domain)
+// d = w - t on every stored cell of a coarse level (written over t): the
+// increment the coarse-grid correction prolongs (Fig. 1 and Fig. 6)
 template <class T>
-__global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ w,
-                          const T* __restrict__ t, Geo gc) {
+__global__ void k_diff(const T* __restrict__ w, T* __restrict__ t, Geo gc) {
+  int q = blockIdx.y;
+  Box Bc = seg_box(gc, q);
+  int me = gc.m;
+  int x, y, z;
+  if (!cell_of((long long)blockIdx.x * blockDim.x + threadIdx.x, me, me, me, x, y, z)) return;
+  int i = Bc.o[0] + x, j = Bc.o[1] + y, k = Bc.o[2] + z;
+  if (!in_dom(gc.n, i, j, k)) return;
+  long long id = at(gc, Bc, i, j, k);
+  t[id] = w[id] - t[id];
+}
+
+// u += P(d) on C and the GSR ghosts (every stored cell inside the domain)
+template <class T>
+__global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ d, Geo gc) {
   int q = blockIdx.y;
   Box B = seg_box(gu, q), Bc = seg_box(gc, q);
   int me = gu.m;
@@ -163,10 +177,9 @@ __global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ w,
   if (!cell_of((long long)blockIdx.x * blockDim.x + threadIdx.x, me, me, me, x, y, z)) return;
   int i = B.o[0] + x, j = B.o[1] + y, k = B.o[2] + z;
   if (!in_dom(gu.n, i, j, k)) return;
-  if (gu.ghost == 0 && (x >= gu.n || y >= gu.n || z >= gu.n)) return;
   long long pc = at(gc, Bc, i >> 1, j >> 1, k >> 1);
   long long id = at(gu, B, i, j, k);
-  u[id] = (T)(u[id] + (w[pc] - t[pc]));
+  u[id] = (T)(u[id] + d[pc]);
 }
 
 // FMG interpolation onto C and the GSR ghosts
@@ -244,16 +257,16 @@ __global__ void k_gather(double* __restrict__ out, const T* __restrict__ u, Geo 
 // ---------------------------------------------------------------------------
 // outer loop of the mixed-precision solve (FP64 residual and update)
 
-// r = (float)(f - L_h u), all in FP64; u == nullptr means u = 0
-__global__ void k_resid64_to32(const double* __restrict__ f, const double* __restrict__ u, int n,
-                               float* __restrict__ r) {
+// r = (float)(f - L_h u), all in FP64; has_u == 0 means u = 0
+__global__ void k_resid64_to32(const double* __restrict__ f, const double* __restrict__ u,
+                               int has_u, int n, float* __restrict__ r) {
   Geo G = global_geo(n);
   Box B = seg_box(G, 0);
   int x, y, z;
   if (!cell_of((long long)blockIdx.x * blockDim.x + threadIdx.x, n, n, n, x, y, z)) return;
   long long id = at(G, B, x, y, z);
   double v = f[id];
-  if (u) v -= apply_L<double, double>(u, G, B, x, y, z);
+  if (has_u) v -= apply_L<double, double>(u, G, B, x, y, z);
   r[id] = (float)v;
 }
 

@@ -36,10 +36,21 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _ScheduleStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("bytes", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+class _KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 _lib = None
 SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_destroy",
-           "fmg_solve", "fmg_plan_workspace_bytes", "fmg_last_error", "fmg_op_apply",
-           "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
+           "fmg_solve", "fmg_plan_workspace_bytes", "fmg_plan_profile", "fmg_plan_profile_read", "fmg_schedule_model",
+           "fmg_last_error", "fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict",
+           "fmg_op_interp"]
 
 
 def lib():
@@ -63,6 +74,13 @@ def lib():
     L.fmg_solve.restype = i32
     L.fmg_plan_workspace_bytes.argtypes = [vp]
     L.fmg_plan_workspace_bytes.restype = ctypes.c_int64
+    L.fmg_plan_profile.argtypes = [vp, i32]
+    L.fmg_plan_profile.restype = i32
+    L.fmg_plan_profile_read.argtypes = [vp, ctypes.POINTER(_KernelStat), i32,
+                                        ctypes.POINTER(i32)]
+    L.fmg_plan_profile_read.restype = i32
+    L.fmg_schedule_model.argtypes = [i32, pp, ctypes.POINTER(_ScheduleStat)]
+    L.fmg_schedule_model.restype = i32
     L.fmg_last_error.argtypes = []
     L.fmg_last_error.restype = ctypes.c_char_p
     L.fmg_op_apply.argtypes = [vp, i32, vp, vp]
@@ -96,6 +114,15 @@ def check_params(N, **kw):
     p, keep = make_params(**kw)
     st = lib().fmg_check_params(N, ctypes.byref(p))
     return st, (lib().fmg_last_error().decode() if st else "")
+
+
+def schedule_model(N, **kw):
+    """Host-only walk of one solve's launches: (launches, algorithmic bytes,
+    workspace bytes).  Raises FMGError on invalid parameters."""
+    p, keep = make_params(**kw)
+    st = _ScheduleStat()
+    _check(lib().fmg_schedule_model(N, ctypes.byref(p), ctypes.byref(st)))
+    return st.launches, st.bytes, st.workspace_bytes
 
 
 def _stream(stream):
@@ -135,6 +162,19 @@ class Plan:
             u = torch.empty_like(f)
         _check(lib().fmg_plan_execute(self._h, _dev(f, self.N), _dev(u, self.N), _stream(stream)))
         return u
+
+    def profile(self, enable=True):
+        """Start (or stop) per-launch event timing; clears pending records."""
+        _check(lib().fmg_plan_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms, algorithmic bytes)} since the last read."""
+        cap = 64
+        buf = (_KernelStat * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().fmg_plan_profile_read(self._h, buf, cap, ctypes.byref(cnt)))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].bytes)
+                for i in range(min(cnt.value, cap))}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -77,3 +77,52 @@ def test_null_params_and_plan():
     assert L.fmg_plan_destroy(None) == 0
     assert L.fmg_plan_execute(None, None, None, None) == fmg.FMG_EINVAL
     assert L.fmg_plan_workspace_bytes(None) == 0
+
+
+# --- host-only walk of the launch schedule --------------------------------------
+
+MODEL_CASES = [
+    (2, dict(levels=1)),
+    (8, dict(levels=3)),
+    (40, dict(levels=4)),
+    (48, dict(levels=5)),
+    (32, dict(levels=5, sweeps=(0, 0, 0))),
+    (32, dict(levels=5, sweeps=(3, 1, 2))),
+    (32, dict(levels=5, sweeps=(8, 8, 8))),
+    (32, dict(levels=5, sr_levels=2, segments=2, buffers=(2, 2))),
+    (32, dict(levels=5, sr_levels=4, segments=2, buffers=(2, 2, 2, 2))),
+    (32, dict(levels=5, sr_levels=1, segments=4, buffers=(0,))),
+    (32, dict(levels=5, sr_levels=2, segments=1, buffers=(2, 2))),
+    (96, dict(levels=6, sr_levels=2, segments=3, buffers=(2, 2))),
+    (256, dict(levels=8)),
+    (256, dict(levels=8, sr_levels=3, segments=8, buffers=(2, 4, 6))),
+    (512, dict(levels=8, sr_levels=3, segments=16, buffers=(2, 4, 6))),
+]
+
+
+@pytest.mark.parametrize("N,kw", MODEL_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_schedule_walks_without_null_pointers(N, kw, precision):
+    launches, nbytes, ws = fmg.schedule_model(N, precision=precision, **kw)
+    assert launches >= 1
+    assert nbytes > 0
+    # at least f read and u written once per cell
+    assert nbytes >= 16.0 * N ** 3
+
+
+def test_schedule_model_byte_counts():
+    _, g, _ = fmg.schedule_model(256, levels=8)
+    _, s, _ = fmg.schedule_model(256, levels=8, sr_levels=3, segments=8, buffers=(2, 4, 6))
+    _, r, _ = fmg.schedule_model(256, levels=8, sr_levels=3, segments=8, buffers=(2, 4, 6),
+                                 precision="fp32_refined")
+    N3 = 256 ** 3
+    # segmental refinement recomputes buffer cells, the refined solve runs
+    # three FP32 solves plus FP64 residuals
+    assert 60 < g / N3 < 150
+    assert 1.5 < s / g < 3.5
+    assert r > s
+
+
+def test_schedule_model_rejects_invalid():
+    with pytest.raises(fmg.FMGError):
+        fmg.schedule_model(32, levels=5, sr_levels=2, segments=2, buffers=(3, 2))
