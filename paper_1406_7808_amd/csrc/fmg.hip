@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -213,6 +214,7 @@ struct fmg_plan {
   bool fused = true;          // temporally blocked smoother (else single-cell kernels)
   int Lc = 0;                 // global levels 0..Lc run in the persistent coarse kernel
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
+  int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
   long long target_blocks = 1024;  // workgroups a fused launch aims for
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
@@ -299,12 +301,17 @@ template <class X>
 static bool nonnull(const X&) { return true; }
 template <class X>
 static bool nonnull(X* p) { return p != nullptr; }
+static bool geo_ok(const Geo& g) { return g.n >= 1 && g.m >= 1 && g.S >= 1 && g.g >= 1; }
 template <class X>
 static bool nonnull(const SmoothArgs<X>& a) {
-  return a.uin && a.u && a.rhs && a.uin != a.u;
+  return a.uin && a.u && a.rhs && a.uin != a.u && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc) &&
+         a.txw > 2 && a.tyw > 2 && a.ntx >= 1 && a.nty >= 1 && a.ntz >= 1 && a.zc >= 1 &&
+         a.nxcd >= 1;
 }
 template <class X>
-static bool nonnull(const BoxArgs<X>& a) { return a.u && a.rhs && a.d; }
+static bool nonnull(const BoxArgs<X>& a) {
+  return a.u && a.rhs && a.d && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc);
+}
 template <class X>
 static bool nonnull(const CoarseArgs<X>& a) {
   if (!a.Ainv || !a.u[0] || (a.mode == 1 && !a.rt)) return false;
@@ -334,7 +341,7 @@ struct Exec {
   template <class K, class... Args>
   void run_shm(const char* name, double bytes, dim3 grid, dim3 block, size_t shm, K kern,
                Args... args) {
-    if (!(nonnull(args) && ...)) throw hip_error(std::string("internal: null pointer for ") + name);
+    if (!(nonnull(args) && ...)) throw hip_error(std::string("internal: invalid launch arguments for ") + name);
     if (grid.x == 0 || grid.y == 0) throw hip_error(std::string("internal: empty grid for ") + name);
     if (dry) {
       P->model_launches += 1;
@@ -390,25 +397,43 @@ struct Exec {
   // one temporally blocked launch of NS half-sweeps with prologue PRO
   template <int NS, int PRO>
   void smooth_z(int l, const T* rhs, Geo gr, const T* c, Geo gc) {
-    // 64 x 32 tile: 16 wavefronts with 2 rows each (1024 threads)
-    constexpr int BYT = 16, RY = 2, TY = BYT * RY;
-    constexpr int SX = 64 - 2 * NS, SY = TY - 2 * NS;
+    // 1024 threads; one column per thread in FP64 for one sweep per launch
+    // (few enough registers for two workgroups per CU), else two
+    constexpr int NT = 1024, RY = (NS <= 2 && sizeof(T) == 8) ? 1 : 2, NC = NT * RY;
     const Geo& G = H.geo[l];
+    if (PRO != PRO_LOAD && !c) throw hip_error("internal: null coarse increment");
+    SmoothArgs<T> a{};
+    a.uin = H.u[l];
+    a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
+    a.gu = G;
+    H.u[l] = a.u;  // the written copy becomes current
     // every stored cell inside the domain is written, so the new copy is whole
     int wext = cext(l) + 2 * G.ghost;
     if (wext > G.n) wext = G.n;
-    if (PRO != PRO_LOAD && !c) throw hip_error("internal: null coarse increment");
-    SmoothArgs<T> a;
-    a.uin = H.u[l];
-    a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
-    H.u[l] = a.u;  // the written copy becomes current
-    a.gu = G;
     a.rhs = rhs;
     a.gr = gr;
     a.c = c;
     a.gc = gc;
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
+    // tile shape: the fewest loaded columns covering the write region
+    {
+      long long best = -1;
+      for (int tx = 2 * NS + 2; tx <= 256 && tx * (2 * NS + 2) <= NC; ++tx) {
+        int ty = NC / tx;
+        if (ty > wext + 2 * NS) ty = wext + 2 * NS;
+        if (ty < 2 * NS + 2) continue;
+        long long cost = (long long)((wext + tx - 2 * NS - 1) / (tx - 2 * NS)) *
+                         ((wext + ty - 2 * NS - 1) / (ty - 2 * NS)) * tx * ty;
+        if (tx < 16) cost += cost / 4;  // short rows load poorly
+        if (best < 0 || cost < best) {
+          best = cost;
+          a.txw = tx;
+          a.tyw = ty;
+        }
+      }
+    }
+    const int SX = a.txw - 2 * NS, SY = a.tyw - 2 * NS;
     a.ntx = (wext + SX - 1) / SX;
     a.nty = (wext + SY - 1) / SY;
     int ns = nseg(l);
@@ -427,9 +452,9 @@ struct Exec {
     int per = (nt + a.nxcd - 1) / a.nxcd;
     double rd = PRO == PRO_CORRECT ? 1.125 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
-    run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>",
-        bytes, dim3(per * a.nxcd, ns), dim3(64 * BYT), k_smooth_z<T, NS, PRO, BYT, RY, kPrefetch<NS>>,
-        a);
+    run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>", bytes,
+        dim3(per * a.nxcd, ns), dim3(NT),
+        k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, (NS <= 2 ? 8 : 4)>, a);
   }
 
   template <int PRO>
@@ -458,7 +483,7 @@ struct Exec {
                "hipFuncSetAttribute");
       attr_set = true;
     }
-    BoxArgs<T> a;
+    BoxArgs<T> a{};
     a.u = H.u[l];
     a.gu = G;
     a.rhs = rhs;
@@ -521,7 +546,7 @@ struct Exec {
     }
     bool first = true;
     while (st > 0) {
-      int ns = st >= 4 ? 4 : st;
+      int ns = st >= P->max_stages ? P->max_stages : st;
       int pr = first ? pro : PRO_LOAD;
       if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, l, rhs, gr, d, Gc);
       else smooth_z_ns<PRO_LOAD>(ns, l, rhs, gr, d, Gc);
@@ -553,8 +578,17 @@ struct Exec {
     a.nu1 = P->nu1;
     a.nu2 = P->nu2;
     a.alpha = P->alpha;
-    run(mode == 0 ? "k_coarse<fmg>" : "k_coarse<vcycle>", bytes, dim3(1), dim3(kCoarseThreads),
-        k_coarse<T>, a);
+    size_t shm = sizeof(T) * (size_t)coarse_lds_elems(a.n, top, mode);
+    if ((long long)shm > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
+    static bool attr_set = false;  // once per instantiation: allow the device maximum
+    if (!dry && !attr_set) {
+      hipcheck(hipFuncSetAttribute((const void*)k_coarse<T>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max),
+               "hipFuncSetAttribute");
+      attr_set = true;
+    }
+    run_shm(mode == 0 ? "k_coarse<fmg>" : "k_coarse<vcycle>", bytes, dim3(1),
+            dim3(kCoarseThreads), shm, k_coarse<T>, a);
   }
 
 
@@ -686,6 +720,7 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
   if (!P) return fail(FMG_ENOMEM, "host allocation failed");
   P->virt = virt;
   P->lds_max = 160 * 1024;
+  if (const char* e = std::getenv("FMG_MAX_STAGES")) P->max_stages = std::atoi(e) <= 2 ? 2 : 4;
   if (!virt) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)
@@ -707,10 +742,20 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
   P->refine = p->refine_iters;
   P->J.assign(P->L, 0);
   for (int l = P->T + 1; l < P->L; ++l) P->J[l] = p->buffer_schedule[P->L - 1 - l];
-  // coarse global levels: edge up to 16, at most the transition level
+  // coarse global levels: edge up to 16, at most the transition level, and
+  // small enough for the LDS of one workgroup
   P->Lc = 0;
-  while (P->Lc + 1 <= P->T && (N >> (P->L - 2 - P->Lc)) <= 16 && P->Lc + 1 < kCoarseMaxLevels)
-    ++P->Lc;
+  {
+    int nl[kCoarseMaxLevels];
+    size_t esz = P->precision == FMG_FP64 ? sizeof(double) : sizeof(float);
+    for (;;) {
+      int c = P->Lc + 1;
+      if (c > P->T || c >= kCoarseMaxLevels || (N >> (P->L - 1 - c)) > 16) break;
+      for (int l = 0; l <= c; ++l) nl[l] = N >> (P->L - 1 - l);
+      if (esz * (size_t)coarse_lds_elems(nl, c, 0) > (size_t)P->lds_max) break;
+      ++P->Lc;
+    }
+  }
   std::vector<double> inv;
   if (!coarse_inverse(P->n0, inv)) {
     delete P;
@@ -920,6 +965,7 @@ int32_t fmg_op_smooth(double* u, const double* rhs, int32_t n, int32_t nu, void*
   int32_t ret = FMG_OK;
   {
     fmg_plan P;
+    if (const char* e = std::getenv("FMG_MAX_STAGES")) P.max_stages = std::atoi(e) <= 2 ? 2 : 4;
     P.N = n;
     P.L = 1;
     P.T = 0;

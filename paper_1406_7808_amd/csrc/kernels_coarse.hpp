@@ -3,8 +3,10 @@
 // Levels whose grids are small (up to 16^3 cells) are latency bound: a kernel
 // launch per operator costs more than the work.  k_coarse runs every
 // operator of these levels inside one workgroup, with a block barrier between
-// phases, on the same level arrays the other kernels use (they stay resident
-// in L2).  It performs either
+// phases, on copies of the levels held in LDS: it loads what the cycle reads
+// (the top level's u and right-hand side, or the FMG right-hand sides), works
+// in LDS and writes back the top level's u, the only result used outside.
+// It performs either
 //   mode 0: FMG stages 0..top (Fig. 2 of the paper): u_0 = L_0^-1 f_0, then
 //           per level Pi, S^alpha and one FAS V-cycle with rhs f_l, or
 //   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt.
@@ -35,21 +37,54 @@ struct CoarseArgs {
   int nu1, nu2, alpha;
 };
 
+// 1 / (6 + nb) for nb = 0..6 boundary faces (constants, no division)
+template <class T>
+__device__ inline T inv_diag(int nb) {
+  return nb == 0 ? (T)(1.0 / 6.0) : nb == 1 ? (T)(1.0 / 7.0) : nb == 2 ? (T)(1.0 / 8.0)
+       : nb == 3 ? (T)(1.0 / 9.0) : nb == 4 ? (T)(1.0 / 10.0) : nb == 5 ? (T)(1.0 / 11.0)
+       : (T)(1.0 / 12.0);
+}
+
+// Cells of an n^3 level owned by this thread: column (x, y) and planes
+// z0, z0 + zs, ... (zs threads share a column); returns false when idle.
+__device__ inline bool blk_column(int n, int& x, int& y, int& z0, int& zs) {
+  const int n2 = n * n;
+  zs = (int)blockDim.x / n2;
+  if (zs < 1) zs = 1;
+  const int t = threadIdx.x;
+  if (t >= n2 * zs) return false;
+  const int c = t % n2;
+  z0 = t / n2;
+  y = c / n;
+  x = c - y * n;
+  return true;
+}
+
+// nu red-black sweeps in place (n <= 32 so every column has an owner)
 template <class T>
 __device__ void blk_gs(T* u, const T* rhs, int n, int nu) {
-  const Geo G = global_geo(n);
-  const Box B = seg_box(G, 0);
-  const int cnt = n * n * n, n2 = n * n;
   const double h = 1.0 / (double)n;
   const T h2 = (T)(h * h);
+  int x = 0, y = 0, z0 = 0, zs = 1;
+  const bool on = blk_column(n, x, y, z0, zs);
+  const int n2 = n * n;
+  const int bxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) {
-      for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
-        int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
-        if (((x + y + z) & 1) != col) continue;
-        int nb;
-        T s = nb_sum<T, T>(u, G, B, x, y, z, nb);
-        u[c] = (s - h2 * rhs[c]) / (T)(6 + nb);
+      if (on) {
+        for (int z = z0; z < n; z += zs) {
+          if (((x + y + z) & 1) != col) continue;
+          const int c = (z * n + y) * n + x;
+          T s = 0;
+          if (x > 0) s += u[c - 1];
+          if (x < n - 1) s += u[c + 1];
+          if (y > 0) s += u[c - n];
+          if (y < n - 1) s += u[c + n];
+          if (z > 0) s += u[c - n2];
+          if (z < n - 1) s += u[c + n2];
+          const int nb = bxy + (z == 0) + (z == n - 1);
+          u[c] = (s - h2 * rhs[c]) * inv_diag<T>(nb);
+        }
       }
       __syncthreads();
     }
@@ -91,12 +126,14 @@ __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc
 // u += P(w - t): the increment is formed per fine cell from the coarse pair
 template <class T>
 __device__ void blk_correct(T* u, int n, const T* w, const T* t) {
-  const int nc = n / 2, n2 = n * n;
-  const int cnt = n * n2;
-  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
-    int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
-    int pc = ((z >> 1) * nc + (y >> 1)) * nc + (x >> 1);
-    u[c] = (T)(u[c] + (w[pc] - t[pc]));
+  const int nc = n / 2;
+  int x = 0, y = 0, z0 = 0, zs = 1;
+  if (blk_column(n, x, y, z0, zs)) {
+    for (int z = z0; z < n; z += zs) {
+      const int pc = ((z >> 1) * nc + (y >> 1)) * nc + (x >> 1);
+      const int c = (z * n + y) * n + x;
+      u[c] = (T)(u[c] + (w[pc] - t[pc]));
+    }
   }
   __syncthreads();
 }
@@ -160,18 +197,64 @@ __device__ void blk_vcycle(const CoarseArgs<T>& a, int top, const T* rt) {
   }
 }
 
+// LDS elements k_coarse needs for levels 0..top with the given edges
+__host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode) {
+  int e = 0;
+  for (int l = 0; l <= top; ++l) {
+    int c = n[l] * n[l] * n[l];
+    e += c;                          // u
+    if (l < top) e += 2 * c;         // t, r
+    if (mode == 0) e += c;           // f
+  }
+  if (mode == 1) e += n[top] * n[top] * n[top];  // rhs of the top level
+  return e;
+}
+
 template <class T>
-__global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> a) {
+__global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  // carve the LDS copies of every level
+  CoarseArgs<T> a = g;
+  int off = 0;
+  for (int l = 0; l <= g.top; ++l) {
+    int c = g.n[l] * g.n[l] * g.n[l];
+    a.u[l] = sm + off;
+    off += c;
+    if (l < g.top) {
+      a.t[l] = sm + off;
+      off += c;
+      a.r[l] = sm + off;
+      off += c;
+    }
+    if (g.mode == 0) {
+      T* fl = sm + off;
+      off += c;
+      for (int i = threadIdx.x; i < c; i += blockDim.x) fl[i] = g.f[l][i];
+      a.f[l] = fl;
+    }
+  }
+  const int ct = g.n[g.top] * g.n[g.top] * g.n[g.top];
+  if (g.mode == 1) {
+    T* rt = sm + off;
+    for (int i = threadIdx.x; i < ct; i += blockDim.x) {
+      rt[i] = g.rt[i];
+      a.u[g.top][i] = g.u[g.top][i];
+    }
+    a.rt = rt;
+  }
+  __syncthreads();
   if (a.mode == 1) {
     blk_vcycle(a, a.top, a.rt);
-    return;
+  } else {
+    blk_coarse_solve(a.u[0], a.f[0], a.Ainv, a.mm);
+    for (int l = 1; l <= a.top; ++l) {
+      blk_interp(a.u[l], a.n[l], a.u[l - 1]);
+      blk_gs(a.u[l], a.f[l], a.n[l], a.alpha);
+      blk_vcycle(a, l, a.f[l]);
+    }
   }
-  blk_coarse_solve(a.u[0], a.f[0], a.Ainv, a.mm);
-  for (int l = 1; l <= a.top; ++l) {
-    blk_interp(a.u[l], a.n[l], a.u[l - 1]);
-    blk_gs(a.u[l], a.f[l], a.n[l], a.alpha);
-    blk_vcycle(a, l, a.f[l]);
-  }
+  for (int i = threadIdx.x; i < ct; i += blockDim.x) g.u[g.top][i] = a.u[g.top][i];
 }
 
 }  // namespace fmg

@@ -4,8 +4,9 @@
 // k_smooth_z applies NS half-sweeps (NS/2 red-black sweeps, red first) to the
 // compute region C of every segment of a level in one pass over HBM:
 //
-//  * a workgroup owns an xy tile of 64 x TY columns (TY = BYT * RY: BYT
-//    wavefronts, RY rows per thread) and marches through a z chunk;
+//  * a workgroup owns an xy tile of txw x tyw columns (chosen per level to fit
+//    the compute regions with little waste; RY columns per thread) and
+//    marches through a z chunk;
 //  * the planes of the z window live in registers: at step p the thread holds
 //    plane p, and half-sweep s (s = 1..NS) updates plane p - s, so the NS
 //    half-sweeps run as a wavefront in z;
@@ -47,23 +48,24 @@ struct SmoothArgs {
   const T* c;   // coarse d = w - t (correct)
   Geo gc;
   T h2;
+  int txw, tyw;       // tile extent in x and y (columns, halo included)
   int ntx, nty, ntz;  // tiles per dimension of the write region
   int zc;             // planes per z chunk
   int nxcd;           // blocks are dealt to this many L2 domains in turn
 };
 
-template <class T, int NS, int PRO, int BYT, int RY, int PF>
-__global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
-  constexpr int TX = 64, TY = BYT * RY, H = NS;
-  constexpr int SX = TX - 2 * H, SY = TY - 2 * H;
-  static_assert(SX > 0 && SY > 0, "tile too small for the number of stages");
+template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_smooth_z(SmoothArgs<T> a) {
+  constexpr int H = NS, NC = NT * RY;
   static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT, "interpolation has its own kernel");
-  __shared__ T lds[2][TY][TX + 1];  // neighbour exchange, one buffer per stage parity
+  __shared__ T lds[2][NC];  // neighbour exchange, one plane per stage parity
 
   const Geo gu = a.gu;
   const int q = blockIdx.y;
   const Box B = seg_box(gu, q);
   const int n = gu.n;
+  const int txw = a.txw, tyw = a.tyw, sx = txw - 2 * H, sy = tyw - 2 * H;
   // blocks are dealt round-robin to the L2 domains: give each domain a
   // contiguous range of tiles so neighbouring tiles share an L2
   int tid = blockIdx.x;
@@ -82,21 +84,15 @@ __global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
     wlo[d] = B.o[d] < 0 ? 0 : B.o[d];
     whi[d] = B.o[d] + gu.m > n ? n : B.o[d] + gu.m;
   }
-  const int ox = wlo[0] + ti * SX, oy = wlo[1] + tj * SY, oz = wlo[2] + tk * a.zc;
+  const int ox = wlo[0] + ti * sx, oy = wlo[1] + tj * sy, oz = wlo[2] + tk * a.zc;
   if (ox >= whi[0] || oy >= whi[1] || oz >= whi[2]) return;
   const int oz1 = oz + a.zc < whi[2] ? oz + a.zc : whi[2];
   const long long mm = (long long)gu.m * gu.m;
-  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
 
   // steps p0..p1, padded to a multiple of PF: the padding steps only touch
   // planes past the chunk, whose results are never stored
   const int p0 = oz - NS, p1 = oz1 - 1 + NS;
   const int nsteps = ((p1 - p0 + 1) + PF - 1) / PF * PF;
-
-  const int x = ox - H + lane;
-  const bool xs = x >= wlo[0] && x < whi[0];
-  const bool xc = x >= B.a[0] && x < B.b[0];
-  const int nbx = (x == 0) + (x == n - 1);
 
   const Box Br = seg_box(a.gr, q);
   const Box Bc = seg_box(a.gc, q);
@@ -107,29 +103,29 @@ __global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
   const long long rmm = (long long)a.gr.m * a.gr.m;
   const long long cmm = (long long)a.gc.m * a.gc.m;
 
+  // tile columns are numbered row-major over txw x tyw; thread t owns
+  // columns t, t + NT, ...
   T U[NS + 2][RY], F[NS + 1][RY];
   T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY];  // ring of planes in flight
-  int ys[RY], uo[RY], ro[RY], co[RY];
-  unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge
-  T inv[RY];        // 1 / (6 + b_c) away from the z walls
-  int nbxy[RY];     // boundary faces in x and y
+  int xr[RY], ys[RY], uo[RY], ci[RY];
+  unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
+                    // bits 4-6 boundary faces in x and y
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    int ly = wy + BYT * r;
-    int y = oy - H + ly;
+    const int c = threadIdx.x + NT * r;
+    const bool col = c < txw * tyw;
+    const int cy = c / txw, cx = c - cy * txw;
+    const int x = ox - H + cx, y = oy - H + cy;
+    ci[r] = col ? c : 0;
+    xr[r] = x;
     ys[r] = y;
-    bool ysok = y >= wlo[1] && y < whi[1];
-    bool yc = y >= B.a[1] && y < B.b[1];
-    bool yo = ly >= H && ly < TY - H;
-    bool xo = lane >= H && lane < TX - H;
-    bool inner = lane > 0 && lane < TX - 1 && ly > 0 && ly < TY - 1;
-    ok[r] = (xs && ysok ? 1u : 0u) | (xc && yc ? 2u : 0u) | (xo && yo && xs && ysok ? 4u : 0u) |
-            (inner ? 8u : 0u);
+    const bool st = col && x >= wlo[0] && x < whi[0] && y >= wlo[1] && y < whi[1];
+    const bool inc = col && x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1];
+    const bool outp = st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H;
+    const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
+    const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+    ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4);
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
-    ro[r] = (y - Br.o[1]) * a.gr.m + (x - Br.o[0]);
-    co[r] = ((y >> 1) - Bc.o[1]) * a.gc.m + ((x >> 1) - Bc.o[0]);
-    nbxy[r] = nbx + (y == 0) + (y == n - 1);
-    inv[r] = (T)1 / (T)(6 + nbxy[r]);
 #pragma unroll
     for (int j = 0; j < NS + 2; ++j) U[j][r] = 0;
 #pragma unroll
@@ -156,8 +152,9 @@ __global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
       vu |= (v ? 1u : 0u) << r;
       vf |= (w ? 1u : 0u) << r;
       qu[r] = ub[v ? pu + uo[r] : 0];
-      if (PRO == PRO_CORRECT) qd[r] = cd[v ? pc + co[r] : 0];
-      qf[r] = rb[w ? pr + ro[r] : 0];
+      if (PRO == PRO_CORRECT)
+        qd[r] = cd[v ? pc + ((ys[r] >> 1) - Bc.o[1]) * a.gc.m + ((xr[r] >> 1) - Bc.o[0]) : 0];
+      qf[r] = rb[w ? pr + (ys[r] - Br.o[1]) * a.gr.m + (xr[r] - Br.o[0]) : 0];
     }
   };
 
@@ -189,21 +186,22 @@ __global__ void __launch_bounds__(64 * BYT) k_smooth_z(SmoothArgs<T> a) {
         const int col = (s - 1) & 1;
         const int b = s & 1;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) lds[b][wy + BYT * r][lane] = U[s][r];
+        for (int r = 0; r < RY; ++r) lds[b][ci[r]] = U[s][r];
         __syncthreads();
         const bool zin = zp >= B.a[2] && zp < B.b[2];
         const int nbz = (zp == 0) + (zp == n - 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-          const int ly = wy + BYT * r;
-          const bool act = zin && ((ok[r] & 10u) == 10u) && (((x + ys[r] + zp) & 1) == col);
+          const bool act = zin && ((ok[r] & 10u) == 10u) && (((xr[r] + ys[r] + zp) & 1) == col);
           if (act) {
-            T sum = lds[b][ly][lane - 1] + lds[b][ly][lane + 1] + lds[b][ly - 1][lane] +
-                    lds[b][ly + 1][lane] + U[s - 1][r] + U[s + 1][r];
-            if (nbz == 0)  // uniform across the block
-              U[s][r] = (sum - a.h2 * F[s][r]) * inv[r];
+            const int c = ci[r];
+            T sum = lds[b][c - 1] + lds[b][c + 1] + lds[b][c - txw] + lds[b][c + txw] +
+                    U[s - 1][r] + U[s + 1][r];
+            const int nb = (int)(ok[r] >> 4) + nbz;
+            if (nb == 0)
+              U[s][r] = (sum - a.h2 * F[s][r]) * (T)(1.0 / 6.0);
             else
-              U[s][r] = (sum - a.h2 * F[s][r]) * ((T)1 / (T)(6 + nbxy[r] + nbz));
+              U[s][r] = (sum - a.h2 * F[s][r]) / (T)(6 + nb);
           }
         }
       }

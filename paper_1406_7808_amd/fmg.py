@@ -10,7 +10,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libfmg.so")
+_SO = os.environ.get("FMG_LIB") or os.path.join(_HERE, "libfmg.so")
 
 FMG_OK, FMG_EINVAL, FMG_ENOMEM, FMG_EHIP, FMG_ENOTSUP = 0, -1, -2, -3, -4
 PRECISION = {"fp64": 0, "fp32_refined": 1}
