@@ -579,11 +579,12 @@ struct Exec {
     a.nu2 = P->nu2;
     a.alpha = P->alpha;
     size_t shm = sizeof(T) * (size_t)coarse_lds_elems(a.n, top, mode);
-    if ((long long)shm > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
+    if ((long long)shm + 1024 > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
     static bool attr_set = false;  // once per instantiation: allow the device maximum
     if (!dry && !attr_set) {
+      // the kernel also holds a small static LDS block (level offsets)
       hipcheck(hipFuncSetAttribute((const void*)k_coarse<T>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max - 1024),
                "hipFuncSetAttribute");
       attr_set = true;
     }
@@ -752,7 +753,7 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
       int c = P->Lc + 1;
       if (c > P->T || c >= kCoarseMaxLevels || (N >> (P->L - 1 - c)) > 16) break;
       for (int l = 0; l <= c; ++l) nl[l] = N >> (P->L - 1 - l);
-      if (esz * (size_t)coarse_lds_elems(nl, c, 0) > (size_t)P->lds_max) break;
+      if (esz * (size_t)coarse_lds_elems(nl, c, 0) + 1024 > (size_t)P->lds_max) break;
       ++P->Lc;
     }
   }

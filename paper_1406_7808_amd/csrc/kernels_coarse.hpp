@@ -180,23 +180,6 @@ __device__ void blk_coarse_solve(T* u0, const T* rhs0, const double* Ainv, int m
   __syncthreads();
 }
 
-// FAS V-cycle from level top with right-hand side rt, down to the exact
-// coarsest solve and back up
-template <class T>
-__device__ void blk_vcycle(const CoarseArgs<T>& a, int top, const T* rt) {
-  for (int l = top; l >= 1; --l) {
-    const T* rhs = (l == top) ? rt : a.r[l];
-    blk_gs(a.u[l], rhs, a.n[l], a.nu1);
-    blk_descend(a.u[l], rhs, a.n[l], a.u[l - 1], a.r[l - 1], a.t[l - 1]);
-  }
-  blk_coarse_solve(a.u[0], top == 0 ? rt : a.r[0], a.Ainv, a.mm);
-  for (int l = 1; l <= top; ++l) {
-    const T* rhs = (l == top) ? rt : a.r[l];
-    blk_correct(a.u[l], a.n[l], a.u[l - 1], a.t[l - 1]);
-    blk_gs(a.u[l], rhs, a.n[l], a.nu2);
-  }
-}
-
 // LDS elements k_coarse needs for levels 0..top with the given edges
 __host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode) {
   int e = 0;
@@ -210,51 +193,90 @@ __host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode)
   return e;
 }
 
+// Level data live in one LDS array; per-level offsets are kept in LDS too,
+// so every access is an LDS instruction (no pointer tables in scratch).
+struct CoarseOffsets {
+  int u[kCoarseMaxLevels], t[kCoarseMaxLevels], r[kCoarseMaxLevels], f[kCoarseMaxLevels];
+  int rt;
+};
+
+// FAS V-cycle from level top with right-hand side sm + rto, down to the
+// exact coarsest solve and back up
+template <class T>
+__device__ void blk_vcycle(T* sm, const CoarseOffsets& o, const CoarseArgs<T>& g, int top,
+                           int rto) {
+  for (int l = top; l >= 1; --l) {
+    T* rhs = sm + ((l == top) ? rto : o.r[l]);
+    blk_gs(sm + o.u[l], rhs, g.n[l], g.nu1);
+    blk_descend(sm + o.u[l], rhs, g.n[l], sm + o.u[l - 1], sm + o.r[l - 1], sm + o.t[l - 1]);
+  }
+  blk_coarse_solve(sm + o.u[0], sm + (top == 0 ? rto : o.r[0]), g.Ainv, g.mm);
+  for (int l = 1; l <= top; ++l) {
+    T* rhs = sm + ((l == top) ? rto : o.r[l]);
+    blk_correct(sm + o.u[l], g.n[l], sm + o.u[l - 1], sm + o.t[l - 1]);
+    blk_gs(sm + o.u[l], rhs, g.n[l], g.nu2);
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  // carve the LDS copies of every level
-  CoarseArgs<T> a = g;
-  int off = 0;
-  for (int l = 0; l <= g.top; ++l) {
-    int c = g.n[l] * g.n[l] * g.n[l];
-    a.u[l] = sm + off;
-    off += c;
-    if (l < g.top) {
-      a.t[l] = sm + off;
+  __shared__ CoarseOffsets o;
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int l = 0; l <= g.top; ++l) {
+      int c = g.n[l] * g.n[l] * g.n[l];
+      o.u[l] = off;
       off += c;
-      a.r[l] = sm + off;
-      off += c;
+      o.t[l] = o.r[l] = 0;
+      if (l < g.top) {
+        o.t[l] = off;
+        off += c;
+        o.r[l] = off;
+        off += c;
+      }
+      o.f[l] = 0;
+      if (g.mode == 0) {
+        o.f[l] = off;
+        off += c;
+      }
     }
-    if (g.mode == 0) {
-      T* fl = sm + off;
-      off += c;
-      for (int i = threadIdx.x; i < c; i += blockDim.x) fl[i] = g.f[l][i];
-      a.f[l] = fl;
-    }
-  }
-  const int ct = g.n[g.top] * g.n[g.top] * g.n[g.top];
-  if (g.mode == 1) {
-    T* rt = sm + off;
-    for (int i = threadIdx.x; i < ct; i += blockDim.x) {
-      rt[i] = g.rt[i];
-      a.u[g.top][i] = g.u[g.top][i];
-    }
-    a.rt = rt;
+    o.rt = off;
   }
   __syncthreads();
-  if (a.mode == 1) {
-    blk_vcycle(a, a.top, a.rt);
+  const int ct = g.n[g.top] * g.n[g.top] * g.n[g.top];
+  if (g.mode == 0) {
+    for (int l = 0; l <= g.top; ++l) {
+      const int c = g.n[l] * g.n[l] * g.n[l];
+      const T* src = g.f[l];
+      T* dst = sm + o.f[l];
+      for (int i = threadIdx.x; i < c; i += blockDim.x) dst[i] = src[i];
+    }
   } else {
-    blk_coarse_solve(a.u[0], a.f[0], a.Ainv, a.mm);
-    for (int l = 1; l <= a.top; ++l) {
-      blk_interp(a.u[l], a.n[l], a.u[l - 1]);
-      blk_gs(a.u[l], a.f[l], a.n[l], a.alpha);
-      blk_vcycle(a, l, a.f[l]);
+    const T* rt = g.rt;
+    const T* ut = g.u[g.top];
+    T* drt = sm + o.rt;
+    T* dut = sm + o.u[g.top];
+    for (int i = threadIdx.x; i < ct; i += blockDim.x) {
+      drt[i] = rt[i];
+      dut[i] = ut[i];
     }
   }
-  for (int i = threadIdx.x; i < ct; i += blockDim.x) g.u[g.top][i] = a.u[g.top][i];
+  __syncthreads();
+  if (g.mode == 1) {
+    blk_vcycle(sm, o, g, g.top, o.rt);
+  } else {
+    blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.Ainv, g.mm);
+    for (int l = 1; l <= g.top; ++l) {
+      blk_interp(sm + o.u[l], g.n[l], sm + o.u[l - 1]);
+      blk_gs(sm + o.u[l], sm + o.f[l], g.n[l], g.alpha);
+      blk_vcycle(sm, o, g, l, o.f[l]);
+    }
+  }
+  T* ut = g.u[g.top];
+  const T* su = sm + o.u[g.top];
+  for (int i = threadIdx.x; i < ct; i += blockDim.x) ut[i] = su[i];
 }
 
 }  // namespace fmg
