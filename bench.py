@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -45,7 +46,20 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, launches_bytes):
+def symbol_pattern(label, dtype="double"):
+    """Regular expression for the demangled symbol (as rocprofv3 prints it)
+    of the kernel instantiation a profile label stands for."""
+    base, _, arg = label.partition("<")
+    arg = arg.rstrip(">")
+    pro = {"load": 0, "interp": 1, "correct": 2}
+    if base == "k_smooth_z":
+        return r"fmg::k_smooth_z<%s, \d+, %d," % (dtype, pro[arg])
+    if base == "k_smooth_box":
+        return r"fmg::k_smooth_box<%s, %d>" % (dtype, pro[arg])
+    return r"fmg::%s[<(]" % base
+
+
+def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from committed rocprofv3 counter
     summaries (profiles/traffic.json), or None when absent or taken on
     other kernel sources."""
@@ -59,6 +73,89 @@ def measured_traffic(kernel, launches_bytes):
     return t.get("bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
+
+
+def counter_pass(args):
+    """The workload run under rocprofv3 --pmc: a few headline solves, then a
+    plain device-to-device copy of COPY_BYTES whose counter readings scale
+    the solver's (FETCH_SIZE / WRITE_SIZE are reported in KiB)."""
+    import torch
+    from paper_1406_7808_amd import fmg
+    from paper_1406_7808_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    f, _, _ = W.fourier(N)
+    fd = torch.from_numpy(f).to(dev)
+    plan = fmg.Plan(N, LEVELS, sr_levels=K, segments=S, buffers=J)
+    u = torch.empty_like(fd)
+    for _ in range(args.steps):
+        plan.execute(fd, u)
+    torch.cuda.synchronize()
+    print("counter pass: %d solves done" % args.steps, flush=True)
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("counter pass: 3 copies of %d bytes done" % COPY_BYTES, flush=True)
+    plan.close()
+    return 0
+
+
+def _pmc_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def traffic_from(fetch_csv, write_csv, kernel, out_path, commands):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of counter_pass:
+    mean KiB per dispatch of `kernel`, scaled by the calibration copy's bytes
+    per KiB (the copy is the largest copyBuffer dispatch of the run), and the
+    same scaled figures for every kernel of the run."""
+    pat = re.compile(symbol_pattern(kernel))
+    res, table = {}, {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _pmc_rows(path) if r.get("Counter_Name") == counter]
+        copies = [r for r in rows if "copyBuffer" in r.get("Kernel_Name", "")]
+        if not copies:
+            raise SystemExit("traffic: no calibration copy in %s" % path)
+        big = max(int(r["Grid_Size"]) for r in copies)
+        copy = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
+        scale = COPY_BYTES / (sum(copy) / len(copy))  # bytes per counted unit
+        kern = [float(r["Counter_Value"]) for r in rows if pat.search(r.get("Kernel_Name", ""))]
+        if not kern:
+            raise SystemExit("traffic: no %s rows for %s in %s" % (counter, kernel, path))
+        res[counter] = {"dispatches": len(kern), "mean_counter": sum(kern) / len(kern),
+                        "copy_mean_counter": sum(copy) / len(copy),
+                        "copy_bytes": COPY_BYTES, "bytes_per_unit": scale,
+                        "bytes_per_launch": sum(kern) / len(kern) * scale}
+        for r in rows:
+            name = r.get("Kernel_Name", "").split("(")[0].replace("void ", "")
+            if "fmg::" not in name:
+                continue
+            key = "%s grid=%s" % (name, r["Grid_Size"])
+            e = table.setdefault(key, {"dispatches": 0})
+            e["dispatches"] = max(e["dispatches"], e.get("_n" + counter, 0) + 1)
+            e["_n" + counter] = e.get("_n" + counter, 0) + 1
+            e[counter + "_MB"] = e.get(counter + "_MB", 0.0) + float(r["Counter_Value"]) * scale / 1e6
+    for e in table.values():
+        n = e.pop("_nFETCH_SIZE", 1)
+        e["FETCH_SIZE_MB"] = round(e.get("FETCH_SIZE_MB", 0.0) / n, 2)
+        n = e.pop("_nWRITE_SIZE", 1)
+        e["WRITE_SIZE_MB"] = round(e.get("WRITE_SIZE_MB", 0.0) / n, 2)
+    out = {"kernel": kernel, "symbol_pattern": symbol_pattern(kernel),
+           "source_hash": source_hash(),
+           "bytes_per_launch": res["FETCH_SIZE"]["bytes_per_launch"]
+           + res["WRITE_SIZE"]["bytes_per_launch"],
+           "counters": res, "per_dispatch_MB": table, "commands": commands}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: v for k, v in out.items() if k != "per_dispatch_MB"}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,11 +164,23 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--variants", default="sr,global,sr32r")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="run the workload for rocprofv3 --pmc (solves + calibration copy)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two counter-pass CSVs")
+    ap.add_argument("--kernel", default="k_smooth_z<load>",
+                    help="profile label whose traffic --traffic-from extracts")
+    ap.add_argument("--commands", default="", help="commands recorded in traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        return traffic_from(args.traffic_from[0], args.traffic_from[1], args.kernel,
+                            os.path.join(ROOT, "profiles", "traffic.json"), args.commands)
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
         return 2
+    if args.counter_pass:
+        return counter_pass(args)
 
     import numpy as np
     import torch
@@ -152,11 +261,11 @@ def main():
     kern = max(by_kernel, key=lambda k: by_kernel[k][1])
     launches, tot_ms, tot_bytes = by_kernel[kern]
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kern, tot_bytes / launches)
+    traffic = measured_traffic(kern)
     kernels = {k: {"launches": v[0] // 3, "ms_per_solve": round(v[1] / 3, 4),
                    "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
-    roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": kern, "symbol": symbol_pattern(kern), "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "launches_per_solve": launches // 3,
                 "avg_launch_us": round(tot_ms / launches * 1e3, 2),
@@ -177,7 +286,8 @@ def main():
     if not args.no_cpu:
         import oracle
         ref, reps, tc = None, 0, time.time()
-        while reps < 4 and (reps == 0 or time.time() - tc < 10.0):
+        # a bounded sample: whole solves until about 12 s have passed
+        while reps < 40 and (reps == 0 or time.time() - tc < 12.0):
             ref = oracle.srfmg(f, LEVELS, K, S, list(J))
             reps += 1
         el = time.time() - tc

@@ -10,9 +10,14 @@
 //   mode 0: FMG stages 0..top (Fig. 2 of the paper): u_0 = L_0^-1 f_0, then
 //           per level Pi, S^alpha and one FAS V-cycle with rhs f_l, or
 //   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt.
-// Every phase applies exactly the per-cell arithmetic of the single-cell
-// kernels; updates of one colour are independent, so the in-place half-sweep
-// is an exact Gauss-Seidel half-sweep.
+//
+// LDS layout: each level's u is stored with a one-cell halo of zeros
+// ((n+2)^3 elements), so a 7-point sum reads its six neighbours without
+// bounds tests (a zero stands for the eliminated Dirichlet ghost; the
+// diagonal 6 + nb carries the boundary).  t, the right-hand sides and f are
+// read point-wise and stored unpadded (n^3, x fastest).  Threads are mapped
+// to the cells of one colour, so every thread of a half-sweep has work and
+// all its loads are issued before its stores.
 #pragma once
 #include "grid.hpp"
 #include "kernels_simple.hpp"
@@ -37,116 +42,163 @@ struct CoarseArgs {
   int nu1, nu2, alpha;
 };
 
+// elements of a level's padded u
+__host__ __device__ inline int coarse_padded(int n) {
+  const int p = n + 2;
+  return p * p * p;
+}
+
+// padded index of cell (x, y, z) of an n^3 level
+__device__ inline int pidx(int n, int x, int y, int z) {
+  const int p = n + 2;
+  return ((z + 1) * p + (y + 1)) * p + (x + 1);
+}
+
 // 1 / (6 + nb) for nb = 0..6 boundary faces (constants, no division)
 template <class T>
 __device__ inline T inv_diag(int nb) {
-  return nb == 0 ? (T)(1.0 / 6.0) : nb == 1 ? (T)(1.0 / 7.0) : nb == 2 ? (T)(1.0 / 8.0)
-       : nb == 3 ? (T)(1.0 / 9.0) : nb == 4 ? (T)(1.0 / 10.0) : nb == 5 ? (T)(1.0 / 11.0)
-       : (T)(1.0 / 12.0);
+  T r = (T)(1.0 / 6.0);
+  r = nb == 1 ? (T)(1.0 / 7.0) : r;
+  r = nb == 2 ? (T)(1.0 / 8.0) : r;
+  r = nb == 3 ? (T)(1.0 / 9.0) : r;
+  r = nb == 4 ? (T)(1.0 / 10.0) : r;
+  r = nb == 5 ? (T)(1.0 / 11.0) : r;
+  r = nb == 6 ? (T)(1.0 / 12.0) : r;
+  return r;
 }
 
-// Cells of an n^3 level owned by this thread: column (x, y) and planes
-// z0, z0 + zs, ... (zs threads share a column); returns false when idle.
-__device__ inline bool blk_column(int n, int& x, int& y, int& z0, int& zs) {
-  const int n2 = n * n;
-  zs = (int)blockDim.x / n2;
-  if (zs < 1) zs = 1;
-  const int t = threadIdx.x;
-  if (t >= n2 * zs) return false;
-  const int c = t % n2;
-  z0 = t / n2;
-  y = c / n;
-  x = c - y * n;
-  return true;
+// one cell of each colour: the i-th cell of colour 0 in (x fastest) order and
+// its x-neighbour, which is the i-th cell of colour 1 (n is even)
+template <class T>
+struct GsCell {
+  int p, c, d;  // padded and plain index of the colour-0 cell; colour-1 offset
+  T inv0, inv1;
+  bool v;
+};
+
+template <class T>
+__device__ inline GsCell<T> gs_cell(int i, int n, int half) {
+  GsCell<T> g;
+  g.v = i < half;
+  const int ii = g.v ? i : 0;  // idle slots read a valid cell and store nothing
+  const int hx = n >> 1;
+  const int row = ii / hx, xh = ii - row * hx;
+  const int z = row / n, y = row - z * n;
+  const int q = (y + z) & 1;
+  const int x0 = 2 * xh + q, x1 = 2 * xh + 1 - q;
+  g.p = pidx(n, x0, y, z);
+  g.c = (z * n + y) * n + x0;
+  g.d = x1 - x0;
+  const int nyz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
+  g.inv0 = inv_diag<T>(nyz + (x0 == 0) + (x0 == n - 1));
+  g.inv1 = inv_diag<T>(nyz + (x1 == 0) + (x1 == n - 1));
+  return g;
 }
 
-// nu red-black sweeps in place (n <= 32 so every column has an owner)
+// Gauss-Seidel update of two cells of colour col: loads, then stores
+template <class T>
+__device__ inline void gs_pair(T* u, const T* rhs, int P, int P2, T h2, int col,
+                               const GsCell<T>& a, const GsCell<T>& b) {
+  const int pa = a.p + (col ? a.d : 0), ca = a.c + (col ? a.d : 0);
+  const int pb = b.p + (col ? b.d : 0), cb = b.c + (col ? b.d : 0);
+  const T sa = ((u[pa - 1] + u[pa + 1]) + (u[pa - P] + u[pa + P])) + (u[pa - P2] + u[pa + P2]);
+  const T sb = ((u[pb - 1] + u[pb + 1]) + (u[pb - P] + u[pb + P])) + (u[pb - P2] + u[pb + P2]);
+  const T ra = rhs[ca], rb = rhs[cb];
+  if (a.v) u[pa] = (sa - h2 * ra) * (col ? a.inv1 : a.inv0);
+  if (b.v) u[pb] = (sb - h2 * rb) * (col ? b.inv1 : b.inv0);
+}
+
+// nu red-black sweeps in place, red ((x + y + z) even) first; u padded
 template <class T>
 __device__ void blk_gs(T* u, const T* rhs, int n, int nu) {
+  if (nu <= 0) return;
   const double h = 1.0 / (double)n;
   const T h2 = (T)(h * h);
-  int x = 0, y = 0, z0 = 0, zs = 1;
-  const bool on = blk_column(n, x, y, z0, zs);
-  const int n2 = n * n;
-  const int bxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+  const int P = n + 2, P2 = P * P, half = n * n * (n >> 1);
+  const int NT = blockDim.x, t = threadIdx.x;
+  const GsCell<T> a = gs_cell<T>(t, n, half), b = gs_cell<T>(t + NT, n, half);
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) {
-      if (on) {
-        for (int z = z0; z < n; z += zs) {
-          if (((x + y + z) & 1) != col) continue;
-          const int c = (z * n + y) * n + x;
-          T s = 0;
-          if (x > 0) s += u[c - 1];
-          if (x < n - 1) s += u[c + 1];
-          if (y > 0) s += u[c - n];
-          if (y < n - 1) s += u[c + n];
-          if (z > 0) s += u[c - n2];
-          if (z < n - 1) s += u[c + n2];
-          const int nb = bxy + (z == 0) + (z == n - 1);
-          u[c] = (s - h2 * rhs[c]) * inv_diag<T>(nb);
-        }
+      if (a.v) gs_pair(u, rhs, P, P2, h2, col, a, b);
+      for (int base = 2 * NT; base < half; base += 2 * NT) {  // levels above 4 NT cells
+        const GsCell<T> e = gs_cell<T>(base + t, n, half), f = gs_cell<T>(base + t + NT, n, half);
+        if (e.v) gs_pair(u, rhs, P, P2, h2, col, e, f);
       }
       __syncthreads();
     }
 }
 
 // uc = R u, rc = R (rhs - L u) on every coarse cell; then t = uc and
-// rc = rc + L_H uc (FAS right-hand side, Eq. 4)
+// rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.
 template <class T>
 __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc) {
-  const Geo G = global_geo(n);
-  const Box B = seg_box(G, 0);
-  const int nc = n / 2, nc2 = nc * nc;
-  const int cc = nc * nc2;
+  const int nc = n / 2, nc2 = nc * nc, cc = nc * nc2;
+  const int P = n + 2, P2 = P * P;
+  const double s2 = (double)n * (double)n;
   for (int c = threadIdx.x; c < cc; c += blockDim.x) {
-    int K = c / nc2, J = (c - K * nc2) / nc, I = c - K * nc2 - J * nc;
+    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
     double su = 0.0, sr = 0.0;
-    for (int cz = 0; cz < 2; ++cz)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
-          int id = (k * n + j) * n + i;
-          su += (double)u[id];
-          sr += (double)rhs[id] - apply_L<T, double>(u, G, B, i, j, k);
-        }
-    uc[c] = (T)(su / 8.0);
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+      const int p = pidx(n, i, j, k);
+      const double v = (double)u[p];
+      const double s = (((double)u[p - 1] + (double)u[p + 1]) +
+                         ((double)u[p - P] + (double)u[p + P])) +
+                       ((double)u[p - P2] + (double)u[p + P2]);
+      const int nb = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
+      su += v;
+      sr += (double)rhs[(k * n + j) * n + i] - (s - (double)(6 + nb) * v) * s2;
+    }
+    uc[pidx(nc, I, J, K)] = (T)(su / 8.0);
     rc[c] = (T)(sr / 8.0);
   }
   __syncthreads();
-  const Geo Gc = global_geo(nc);
-  const Box Bc = seg_box(Gc, 0);
+  const int Pc = nc + 2, Pc2 = Pc * Pc;
+  const double sc2 = (double)nc * (double)nc;
   for (int c = threadIdx.x; c < cc; c += blockDim.x) {
-    int K = c / nc2, J = (c - K * nc2) / nc, I = c - K * nc2 - J * nc;
-    tc[c] = uc[c];
-    rc[c] = (T)((double)rc[c] + apply_L<T, double>(uc, Gc, Bc, I, J, K));
+    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
+    const int p = pidx(nc, I, J, K);
+    const double v = (double)uc[p];
+    const double s = (((double)uc[p - 1] + (double)uc[p + 1]) +
+                      ((double)uc[p - Pc] + (double)uc[p + Pc])) +
+                     ((double)uc[p - Pc2] + (double)uc[p + Pc2]);
+    const int nb = (I == 0) + (I == nc - 1) + (J == 0) + (J == nc - 1) + (K == 0) + (K == nc - 1);
+    tc[c] = uc[p];
+    rc[c] = (T)((double)rc[c] + (s - (double)(6 + nb) * v) * sc2);
   }
   __syncthreads();
 }
 
-// u += P(w - t): the increment is formed per fine cell from the coarse pair
+// u += P(w - t): the increment of each coarse cell goes to its 8 children;
+// u and w padded, t plain
 template <class T>
 __device__ void blk_correct(T* u, int n, const T* w, const T* t) {
-  const int nc = n / 2;
-  int x = 0, y = 0, z0 = 0, zs = 1;
-  if (blk_column(n, x, y, z0, zs)) {
-    for (int z = z0; z < n; z += zs) {
-      const int pc = ((z >> 1) * nc + (y >> 1)) * nc + (x >> 1);
-      const int c = (z * n + y) * n + x;
-      u[c] = (T)(u[c] + (w[pc] - t[pc]));
-    }
+  const int nc = n / 2, nc2 = nc * nc, cc = nc * nc2;
+  const int P = n + 2, P2 = P * P;
+  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
+    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
+    const T d = w[pidx(nc, I, J, K)] - t[c];
+    const int p = pidx(n, 2 * I, 2 * J, 2 * K);
+    T v[8];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) v[ch] = u[p + (ch >> 2) * P2 + ((ch >> 1) & 1) * P + (ch & 1)];
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch)
+      u[p + (ch >> 2) * P2 + ((ch >> 1) & 1) * P + (ch & 1)] = (T)(v[ch] + d);
   }
   __syncthreads();
 }
 
+// FMG interpolation Pi (trilinear, odd reflection at the boundary) of the
+// padded coarse c onto the padded fine u
 template <class T>
 __device__ void blk_interp(T* u, int n, const T* c) {
-  const Geo G = global_geo(n), Gc = global_geo(n / 2);
-  const Box Bc = seg_box(Gc, 0);
-  const int n2 = n * n, cnt = n * n2;
+  const int n2 = n * n, cnt = n * n2, nc = n / 2;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
-    int f[3] = {x, y, z};
-    int nc = n / 2, p[3], r[3];
+    const int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
+    const int f[3] = {x, y, z};
+    int p[3], r[3];
     for (int d = 0; d < 3; ++d) {
       p[d] = f[d] >> 1;
       r[d] = (f[d] & 1) ? p[d] + 1 : p[d] - 1;
@@ -162,20 +214,21 @@ __device__ void blk_interp(T* u, int n, const T* c) {
             if (id3[d] < 0) { id3[d] = -1 - id3[d]; sign = -sign; }
             else if (id3[d] >= nc) { id3[d] = 2 * nc - 1 - id3[d]; sign = -sign; }
           }
-          s += w * sign * c[at(Gc, Bc, id3[0], id3[1], id3[2])];
+          s += w * sign * c[pidx(nc, id3[0], id3[1], id3[2])];
         }
-    u[i] = s;
+    u[pidx(n, x, y, z)] = s;
   }
-  (void)G;
   __syncthreads();
 }
 
+// exact coarsest solve u0 = A^-1 rhs0 (rhs0 plain, u0 padded)
 template <class T>
-__device__ void blk_coarse_solve(T* u0, const T* rhs0, const double* Ainv, int mm) {
+__device__ void blk_coarse_solve(T* u0, const T* rhs0, int n0, const double* Ainv, int mm) {
   for (int r = threadIdx.x; r < mm; r += blockDim.x) {
     double s = 0.0;
     for (int c = 0; c < mm; ++c) s += Ainv[r * mm + c] * (double)rhs0[c];
-    u0[r] = (T)s;
+    const int z = r / (n0 * n0), y = (r - z * n0 * n0) / n0, x = r - (z * n0 + y) * n0;
+    u0[pidx(n0, x, y, z)] = (T)s;
   }
   __syncthreads();
 }
@@ -184,10 +237,10 @@ __device__ void blk_coarse_solve(T* u0, const T* rhs0, const double* Ainv, int m
 __host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode) {
   int e = 0;
   for (int l = 0; l <= top; ++l) {
-    int c = n[l] * n[l] * n[l];
-    e += c;                          // u
-    if (l < top) e += 2 * c;         // t, r
-    if (mode == 0) e += c;           // f
+    const int c = n[l] * n[l] * n[l];
+    e += coarse_padded(n[l]);  // u
+    if (l < top) e += 2 * c;   // t, r
+    if (mode == 0) e += c;     // f
   }
   if (mode == 1) e += n[top] * n[top] * n[top];  // rhs of the top level
   return e;
@@ -197,7 +250,7 @@ __host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode)
 // so every access is an LDS instruction (no pointer tables in scratch).
 struct CoarseOffsets {
   int u[kCoarseMaxLevels], t[kCoarseMaxLevels], r[kCoarseMaxLevels], f[kCoarseMaxLevels];
-  int rt;
+  int rt, uend;
 };
 
 // FAS V-cycle from level top with right-hand side sm + rto, down to the
@@ -210,11 +263,38 @@ __device__ void blk_vcycle(T* sm, const CoarseOffsets& o, const CoarseArgs<T>& g
     blk_gs(sm + o.u[l], rhs, g.n[l], g.nu1);
     blk_descend(sm + o.u[l], rhs, g.n[l], sm + o.u[l - 1], sm + o.r[l - 1], sm + o.t[l - 1]);
   }
-  blk_coarse_solve(sm + o.u[0], sm + (top == 0 ? rto : o.r[0]), g.Ainv, g.mm);
+  blk_coarse_solve(sm + o.u[0], sm + (top == 0 ? rto : o.r[0]), g.n[0], g.Ainv, g.mm);
   for (int l = 1; l <= top; ++l) {
     T* rhs = sm + ((l == top) ? rto : o.r[l]);
     blk_correct(sm + o.u[l], g.n[l], sm + o.u[l - 1], sm + o.t[l - 1]);
     blk_gs(sm + o.u[l], rhs, g.n[l], g.nu2);
+  }
+}
+
+// copy an n^3 level between global memory (plain) and LDS (padded or plain);
+// up to four loads per thread are in flight before the stores
+template <class T, bool IN, bool PAD>
+__device__ void blk_copy(T* lds, T* glob, int n) {
+  const int n2 = n * n, cnt = n * n2, NT = blockDim.x;
+  for (int base = 0; base < cnt; base += 4 * NT) {
+    T v[4];
+    int li[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = base + threadIdx.x + k * NT;
+      const int ii = i < cnt ? i : 0;
+      const int z = ii / n2, y = (ii - z * n2) / n, x = ii - z * n2 - y * n;
+      li[k] = PAD ? pidx(n, x, y, z) : ii;
+      v[k] = (i < cnt) ? (IN ? glob[ii] : lds[li[k]]) : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = base + threadIdx.x + k * NT;
+      if (i < cnt) {
+        if (IN) lds[li[k]] = v[k];
+        else glob[i] = v[k];
+      }
+    }
   }
 }
 
@@ -226,57 +306,50 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   if (threadIdx.x == 0) {
     int off = 0;
     for (int l = 0; l <= g.top; ++l) {
-      int c = g.n[l] * g.n[l] * g.n[l];
       o.u[l] = off;
-      off += c;
-      o.t[l] = o.r[l] = 0;
+      off += coarse_padded(g.n[l]);
+    }
+    o.uend = off;
+    for (int l = 0; l <= g.top; ++l) {
+      const int c = g.n[l] * g.n[l] * g.n[l];
+      o.t[l] = o.r[l] = o.f[l] = 0;
       if (l < g.top) {
         o.t[l] = off;
         off += c;
         o.r[l] = off;
         off += c;
       }
-      o.f[l] = 0;
-      if (g.mode == 0) {
+    }
+    if (g.mode == 0) {
+      for (int l = 0; l <= g.top; ++l) {
         o.f[l] = off;
-        off += c;
+        off += g.n[l] * g.n[l] * g.n[l];
       }
     }
     o.rt = off;
   }
   __syncthreads();
-  const int ct = g.n[g.top] * g.n[g.top] * g.n[g.top];
+  for (int i = threadIdx.x; i < o.uend; i += blockDim.x) sm[i] = (T)0;  // halos
+  __syncthreads();
   if (g.mode == 0) {
-    for (int l = 0; l <= g.top; ++l) {
-      const int c = g.n[l] * g.n[l] * g.n[l];
-      const T* src = g.f[l];
-      T* dst = sm + o.f[l];
-      for (int i = threadIdx.x; i < c; i += blockDim.x) dst[i] = src[i];
-    }
+    for (int l = 0; l <= g.top; ++l)
+      blk_copy<T, true, false>(sm + o.f[l], const_cast<T*>(g.f[l]), g.n[l]);
   } else {
-    const T* rt = g.rt;
-    const T* ut = g.u[g.top];
-    T* drt = sm + o.rt;
-    T* dut = sm + o.u[g.top];
-    for (int i = threadIdx.x; i < ct; i += blockDim.x) {
-      drt[i] = rt[i];
-      dut[i] = ut[i];
-    }
+    blk_copy<T, true, false>(sm + o.rt, const_cast<T*>(g.rt), g.n[g.top]);
+    blk_copy<T, true, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);
   }
   __syncthreads();
   if (g.mode == 1) {
     blk_vcycle(sm, o, g, g.top, o.rt);
   } else {
-    blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.Ainv, g.mm);
+    blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.n[0], g.Ainv, g.mm);
     for (int l = 1; l <= g.top; ++l) {
       blk_interp(sm + o.u[l], g.n[l], sm + o.u[l - 1]);
       blk_gs(sm + o.u[l], sm + o.f[l], g.n[l], g.alpha);
       blk_vcycle(sm, o, g, l, o.f[l]);
     }
   }
-  T* ut = g.u[g.top];
-  const T* su = sm + o.u[g.top];
-  for (int i = threadIdx.x; i < ct; i += blockDim.x) ut[i] = su[i];
+  blk_copy<T, false, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);
 }
 
 }  // namespace fmg
