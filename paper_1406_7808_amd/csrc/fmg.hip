@@ -25,6 +25,7 @@
 #include "../../include/fmg.h"
 #include "grid.hpp"
 #include "kernels_coarse.hpp"
+#include "kernels_descend.hpp"
 #include "kernels_fused.hpp"
 #include "kernels_simple.hpp"
 
@@ -215,6 +216,7 @@ struct fmg_plan {
   int Lc = 0;                 // global levels 0..Lc run in the persistent coarse kernel
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
   int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
+  bool seg_inplace = true;    // segment levels: in place, one workgroup per segment
   long long target_blocks = 1024;  // workgroups a fused launch aims for
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
@@ -304,13 +306,21 @@ static bool nonnull(X* p) { return p != nullptr; }
 static bool geo_ok(const Geo& g) { return g.n >= 1 && g.m >= 1 && g.S >= 1 && g.g >= 1; }
 template <class X>
 static bool nonnull(const SmoothArgs<X>& a) {
-  return a.uin && a.u && a.rhs && a.uin != a.u && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc) &&
+  return a.uin && a.u && a.rhs && (a.uin != a.u || a.inplace) && geo_ok(a.gu) && geo_ok(a.gr) &&
+         geo_ok(a.gc) &&
          a.txw > 2 && a.tyw > 2 && a.ntx >= 1 && a.nty >= 1 && a.ntz >= 1 && a.zc >= 1 &&
          a.nxcd >= 1;
 }
 template <class X>
+static bool nonnull(const DescArgs<X>& a) {
+  return a.u && a.rhs && a.uc && a.rc && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc) &&
+         a.ctx >= 1 && a.cty >= 1 && (2 * a.ctx + 2) * (2 * a.cty + 2) <= kDescThreads &&
+         a.kc >= 1 && a.ntx >= 1 && a.nty >= 1 && a.ntz >= 1 && a.nxcd >= 1 &&
+         (a.mode == 0 || a.mode == 1);
+}
+template <class X>
 static bool nonnull(const BoxArgs<X>& a) {
-  return a.u && a.rhs && a.d && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc);
+  return a.u && a.rhs && a.d && a.dt && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc);
 }
 template <class X>
 static bool nonnull(const CoarseArgs<X>& a) {
@@ -394,30 +404,41 @@ struct Exec {
             H.u[l], G, rhs, gr, col, h2, ce);
   }
 
-  // one temporally blocked launch of NS half-sweeps with prologue PRO
-  template <int NS, int PRO>
-  void smooth_z(int l, const T* rhs, Geo gr, const T* c, Geo gc) {
-    // 1024 threads; one column per thread in FP64 for one sweep per launch
-    // (few enough registers for two workgroups per CU), else two
-    constexpr int NT = 1024, RY = (NS <= 2 && sizeof(T) == 8) ? 1 : 2, NC = NT * RY;
+  // one temporally blocked launch of NS half-sweeps with prologue PRO; RY
+  // columns per thread; inpl: one workgroup per segment, updated in place
+  template <int NS, int RY, int PRO>
+  void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl) {
+    constexpr int NT = 1024, NC = NT * RY;
+    constexpr int WPE = (NS <= 2 && (RY == 1 || sizeof(T) == 4)) ? 8 : 4;
     const Geo& G = H.geo[l];
-    if (PRO != PRO_LOAD && !c) throw hip_error("internal: null coarse increment");
+    if (PRO != PRO_LOAD && (!c || !ct)) throw hip_error("internal: null coarse increment");
     SmoothArgs<T> a{};
     a.uin = H.u[l];
-    a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
+    a.u = inpl ? H.u[l] : (H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l]);
     a.gu = G;
     H.u[l] = a.u;  // the written copy becomes current
-    // every stored cell inside the domain is written, so the new copy is whole
-    int wext = cext(l) + 2 * G.ghost;
-    if (wext > G.n) wext = G.n;
     a.rhs = rhs;
     a.gr = gr;
     a.c = c;
+    a.ct = ct;
     a.gc = gc;
+    a.inplace = inpl ? 1 : 0;
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
-    // tile shape: the fewest loaded columns covering the write region
-    {
+    int ns = nseg(l);
+    if (inpl) {
+      // one tile covering the largest compute region plus the halo, one chunk
+      const int ce = cext(l);
+      if (!G.ghost || (ce + 2 * NS) * (ce + 2 * NS) > NC)
+        throw hip_error("internal: segment does not fit one in-place tile");
+      a.txw = a.tyw = ce + 2 * NS;
+      a.ntx = a.nty = a.ntz = 1;
+      a.zc = ce;
+    } else {
+      // every stored cell inside the domain is written, so the new copy is whole
+      int wext = cext(l) + 2 * G.ghost;
+      if (wext > G.n) wext = G.n;
+      // tile shape: the fewest loaded columns covering the write region
       long long best = -1;
       for (int tx = 2 * NS + 2; tx <= 256 && tx * (2 * NS + 2) <= NC; ++tx) {
         int ty = NC / tx;
@@ -432,35 +453,46 @@ struct Exec {
           a.tyw = ty;
         }
       }
+      const int SX = a.txw - 2 * NS, SY = a.tyw - 2 * NS;
+      a.ntx = (wext + SX - 1) / SX;
+      a.nty = (wext + SY - 1) / SY;
+      long long bxy = (long long)a.ntx * a.nty * ns;
+      int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
+      // large levels keep chunks at least 2 NS deep (recomputed halo planes);
+      // small, L2-resident levels split finely to shorten the serial z march
+      int zmax = wext <= 64 ? (wext + 1) / 2 : wext / (2 * NS);
+      if (zmax < 1) zmax = 1;
+      if (ntz > zmax) ntz = zmax;
+      if (ntz < 1) ntz = 1;
+      a.zc = (wext + ntz - 1) / ntz;
+      a.ntz = (wext + a.zc - 1) / a.zc;
     }
-    const int SX = a.txw - 2 * NS, SY = a.tyw - 2 * NS;
-    a.ntx = (wext + SX - 1) / SX;
-    a.nty = (wext + SY - 1) / SY;
-    int ns = nseg(l);
-    long long bxy = (long long)a.ntx * a.nty * ns;
-    int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
-    // large levels keep chunks at least 2 NS deep (recomputed halo planes);
-    // small, L2-resident levels split finely to shorten the serial z march
-    int zmax = wext <= 64 ? (wext + 1) / 2 : wext / (2 * NS);
-    if (zmax < 1) zmax = 1;
-    if (ntz > zmax) ntz = zmax;
-    if (ntz < 1) ntz = 1;
-    a.zc = (wext + ntz - 1) / ntz;
-    a.ntz = (wext + a.zc - 1) / a.zc;
     a.nxcd = ns > 1 ? 1 : P->nxcd;
     int nt = a.ntx * a.nty * a.ntz;
     int per = (nt + a.nxcd - 1) / a.nxcd;
-    double rd = PRO == PRO_CORRECT ? 1.125 : 1.0;
+    double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
     run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>", bytes,
-        dim3(per * a.nxcd, ns), dim3(NT),
-        k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, (NS <= 2 ? 8 : 4)>, a);
+        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE>, a);
   }
 
   template <int PRO>
-  void smooth_z_ns(int ns, int l, const T* rhs, Geo gr, const T* c, Geo gc) {
-    if (ns == 2) smooth_z<2, PRO>(l, rhs, gr, c, gc);
-    else smooth_z<4, PRO>(l, rhs, gr, c, gc);
+  void smooth_z_ns(int ns, bool inpl, int l, const T* rhs, Geo gr, const T* c, const T* ct,
+                   Geo gc) {
+    // one column per thread for FP64 two-stage passes over two copies (few
+    // enough registers for two workgroups per CU), else two
+    constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
+    if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
+    else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true);
+    else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl);
+  }
+
+  // can level l's segments be smoothed in place, one workgroup each, with
+  // four half-sweeps per pass?
+  bool seg_inplace(int l) const {
+    const Geo& G = H.geo[l];
+    const int ce = cext(l) + 8;
+    return P->seg_inplace && G.ghost && ce * ce <= 2 * 1024;
   }
 
   // does a segment's whole storage box fit the box-resident smoother?
@@ -473,7 +505,7 @@ struct Exec {
   }
 
   template <int PRO>
-  void smooth_box_pro(int l, const T* rhs, Geo gr, int nu, const T* d, Geo gc) {
+  void smooth_box_pro(int l, const T* rhs, Geo gr, int nu, const T* d, const T* dt, Geo gc) {
     const Geo& G = H.geo[l];
     size_t shm = (size_t)cube(G.m) * sizeof(T);
     static bool attr_set = false;  // once per instantiation: allow the device maximum
@@ -489,19 +521,21 @@ struct Exec {
     a.rhs = rhs;
     a.gr = gr;
     a.d = PRO == PRO_CORRECT ? d : H.u[l];
+    a.dt = PRO == PRO_CORRECT ? dt : H.u[l];
     a.gc = gc;
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
     a.nu = nu;
-    double rd = PRO == PRO_CORRECT ? 1.125 : 1.0;
+    double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
     run_shm(PRO == PRO_CORRECT ? "k_smooth_box<correct>" : "k_smooth_box<load>",
-            sizeof(T) * (1.0 + rd) * c_cells(G) + sizeof(T) * nu * c_cells(G), dim3(nseg(l)),
+            sizeof(T) * (2.0 + rd) * c_cells(G), dim3(nseg(l)),
             dim3(kBoxThreads), shm, k_smooth_box<T, PRO>, a);
   }
 
-  void smooth_box(int l, const T* rhs, Geo gr, int nu, int pro, const T* d, Geo gc) {
-    if (pro == PRO_CORRECT) smooth_box_pro<PRO_CORRECT>(l, rhs, gr, nu, d, gc);
-    else smooth_box_pro<PRO_LOAD>(l, rhs, gr, nu, d, gc);
+  void smooth_box(int l, const T* rhs, Geo gr, int nu, int pro, const T* d, const T* dt,
+                  Geo gc) {
+    if (pro == PRO_CORRECT) smooth_box_pro<PRO_CORRECT>(l, rhs, gr, nu, d, dt, gc);
+    else smooth_box_pro<PRO_LOAD>(l, rhs, gr, nu, d, dt, gc);
   }
 
   // FMG interpolation onto the current copy of level l (streaming kernel)
@@ -522,34 +556,33 @@ struct Exec {
     lvl = l;
     const Geo& G = H.geo[l];
     const Geo& Gc = H.geo[l > 0 ? l - 1 : 0];
-    const T* d = l > 0 ? H.t[l - 1] : nullptr;
+    // the coarse-grid correction adds w - t of level l-1 (formed per cell)
+    const T* d = l > 0 ? H.u[l - 1] : nullptr;
+    const T* dt = l > 0 ? H.t[l - 1] : nullptr;
     if (pro == PRO_INTERP) {
       interp(l);
       pro = PRO_LOAD;
     }
-    if (pro == PRO_CORRECT) {
-      // d = w - t on the coarse level, over t
-      run("k_diff", 3.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nseg(l - 1)),
-          dim3(kBlock), k_diff<T>, (const T*)H.u[l - 1], H.t[l - 1], Gc);
-    }
     int st = 2 * nu;
     if (st > 0 && P->fused && box_fits(l)) {
-      smooth_box(l, rhs, gr, nu, pro, d, Gc);
+      smooth_box(l, rhs, gr, nu, pro, d, dt, Gc);
       return;
     }
     if (st == 0 || !P->fused) {
       if (pro == PRO_CORRECT)
-        run("k_correct", sizeof(T) * 2.125 * st_cells(G), grid_for(cube(G.m), nseg(l)),
-            dim3(kBlock), k_correct<T>, H.u[l], G, d, Gc);
+        run("k_correct", sizeof(T) * 2.25 * st_cells(G), grid_for(cube(G.m), nseg(l)),
+            dim3(kBlock), k_correct<T>, H.u[l], G, d, dt, Gc);
       smooth_simple(l, rhs, gr, nu);
       return;
     }
     bool first = true;
+    const bool inpl = seg_inplace(l);
+    const int mx = inpl ? 4 : P->max_stages;
     while (st > 0) {
-      int ns = st >= P->max_stages ? P->max_stages : st;
+      int ns = st >= mx ? mx : st;
       int pr = first ? pro : PRO_LOAD;
-      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, l, rhs, gr, d, Gc);
-      else smooth_z_ns<PRO_LOAD>(ns, l, rhs, gr, d, Gc);
+      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc);
+      else smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc);
       st -= ns;
       first = false;
     }
@@ -603,12 +636,64 @@ struct Exec {
     int ns = nseg(l);
     int ce = mode == 0 ? cext(l) / 2 : Gc.n / P->S;
     double coarse = mode == 0 ? c_cells(G) / 8.0 : cube(Gc.n);
-    run("k_resid_restrict", sizeof(T) * (16.0 * coarse + 2.0 * coarse), grid_for(cube(ce), ns),
-        dim3(kBlock), k_resid_restrict<T>, (const T*)H.u[l], G, rhs, gr, H.u[l - 1],
-        H.rhs[l - 1], Gc, mode, ce);
+    double bytes = sizeof(T) * (16.0 * coarse + 2.0 * coarse);
+    // the streaming pass on large targets; small ones are latency bound and
+    // take the one-thread-per-coarse-cell kernel
+    if (P->fused && cube(ce) * ns > 300000) {
+      descend_z(l, rhs, gr, mode, ce, bytes);
+    } else {
+      run("k_resid_restrict", bytes, grid_for(cube(ce), ns), dim3(kBlock), k_resid_restrict<T>,
+          (const T*)H.u[l], G, rhs, gr, H.u[l - 1], H.rhs[l - 1], Gc, mode, ce);
+    }
     int nsc = mode == 0 ? ns : 1;
     run("k_coarse_rhs", 4.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nsc), dim3(kBlock),
         k_coarse_rhs<T>, (const T*)H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, whole_f);
+  }
+
+  // residual + restriction as one streaming pass (k_descend_z); ce is the
+  // largest per-segment extent of the coarse target region
+  void descend_z(int l, const T* rhs, Geo gr, int mode, int ce, double bytes) {
+    constexpr int RY = 1, NC = kDescThreads * RY;
+    const Geo& G = H.geo[l];
+    DescArgs<T> a{};
+    a.u = H.u[l];
+    a.gu = G;
+    a.rhs = rhs;
+    a.gr = gr;
+    a.uc = H.u[l - 1];
+    a.rc = H.rhs[l - 1];
+    a.gc = H.geo[l - 1];
+    a.mode = mode;
+    // tile shape: the fewest loaded fine columns covering the target
+    long long best = -1;
+    for (int tx = 1; tx <= ce && 2 * tx + 2 <= NC / 4; ++tx) {
+      int ty = (NC / (2 * tx + 2) - 2) / 2;
+      if (ty > ce) ty = ce;
+      if (ty < 1) continue;
+      long long cost = (long long)((ce + tx - 1) / tx) * ((ce + ty - 1) / ty) * (2 * tx + 2) *
+                       (2 * ty + 2);
+      if (tx < 8) cost += cost / 4;  // short rows load poorly
+      if (best < 0 || cost <= best) {  // ties: the longer rows
+        best = cost;
+        a.ctx = tx;
+        a.cty = ty;
+      }
+    }
+    a.ntx = (ce + a.ctx - 1) / a.ctx;
+    a.nty = (ce + a.cty - 1) / a.cty;
+    int ns = nseg(l);
+    long long bxy = (long long)a.ntx * a.nty * ns;
+    int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
+    // chunks of at least 8 coarse planes: each re-reads two halo fine planes
+    int zmax = ce / 8 < 1 ? 1 : ce / 8;
+    if (ntz > zmax) ntz = zmax;
+    if (ntz < 1) ntz = 1;
+    a.kc = (ce + ntz - 1) / ntz;
+    a.ntz = (ce + a.kc - 1) / a.kc;
+    a.nxcd = ns > 1 ? 1 : P->nxcd;
+    int nt = a.ntx * a.nty * a.ntz;
+    int per = (nt + a.nxcd - 1) / a.nxcd;
+    run("k_descend_z", bytes, dim3(per * a.nxcd, ns), dim3(kDescThreads), k_descend_z<T, RY, 2>, a);
   }
 
   // FAS V-cycle on global level l with right-hand side rhs (Fig. 1)
@@ -722,6 +807,7 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
   P->virt = virt;
   P->lds_max = 160 * 1024;
   if (const char* e = std::getenv("FMG_MAX_STAGES")) P->max_stages = std::atoi(e) <= 2 ? 2 : 4;
+  if (const char* e = std::getenv("FMG_SEG_INPLACE")) P->seg_inplace = std::atoi(e) != 0;
   if (!virt) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)

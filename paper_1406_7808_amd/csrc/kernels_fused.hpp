@@ -22,6 +22,12 @@
 //    overlap, so an in-place update would let a tile read halo cells that its
 //    neighbour has already advanced.  Every stored cell inside the domain is
 //    written (GSR ghosts unchanged), so the written copy is complete;
+//  * in place (inplace = 1) when one workgroup holds a whole segment (one
+//    tile covering C plus the halo, one z chunk): segments own their storage
+//    and each plane is read before it is written, so nothing else can see a
+//    partial update.  Only C is written -- and, after a correction prologue,
+//    the GSR ghosts, whose corrected values are final as they are never
+//    smoothed;
 //  * the load stage is either u itself or u + P(d) with d = w - t on the
 //    coarse level, the coarse-grid correction of Fig. 1 and Fig. 6 of the
 //    paper (piecewise-constant prolongation), applied on C and the GSR ghosts
@@ -45,13 +51,15 @@ struct SmoothArgs {
   Geo gu;
   const T* rhs;
   Geo gr;
-  const T* c;   // coarse d = w - t (correct)
+  const T* c;   // coarse w (correct: the increment is w - t)
+  const T* ct;  // coarse t (correct)
   Geo gc;
   T h2;
   int txw, tyw;       // tile extent in x and y (columns, halo included)
   int ntx, nty, ntz;  // tiles per dimension of the write region
   int zc;             // planes per z chunk
   int nxcd;           // blocks are dealt to this many L2 domains in turn
+  int inplace;        // 1: one workgroup per segment, u updated in place
 };
 
 template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE>
@@ -78,20 +86,29 @@ k_smooth_z(SmoothArgs<T> a) {
   }
   const int ti = tid % a.ntx, tj = (tid / a.ntx) % a.nty, tk = tid / (a.ntx * a.nty);
 
-  // write region: every stored cell inside the domain
-  int wlo[3], whi[3];
+  // load region: every stored cell inside the domain.  The tiles partition
+  // the load region (two copies) or C (in place); in place, a correction
+  // also stores the ghost layer around C.
+  const bool inpl = a.inplace != 0;
+  int wlo[3], whi[3], glo[3], ghi[3];
   for (int d = 0; d < 3; ++d) {
     wlo[d] = B.o[d] < 0 ? 0 : B.o[d];
     whi[d] = B.o[d] + gu.m > n ? n : B.o[d] + gu.m;
+    glo[d] = B.a[d] - 1 < 0 ? 0 : B.a[d] - 1;
+    ghi[d] = B.b[d] + 1 > n ? n : B.b[d] + 1;
   }
-  const int ox = wlo[0] + ti * sx, oy = wlo[1] + tj * sy, oz = wlo[2] + tk * a.zc;
-  if (ox >= whi[0] || oy >= whi[1] || oz >= whi[2]) return;
-  const int oz1 = oz + a.zc < whi[2] ? oz + a.zc : whi[2];
+  const int tx0 = inpl ? B.a[0] : wlo[0], ty0 = inpl ? B.a[1] : wlo[1];
+  const int tz0 = inpl ? B.a[2] : wlo[2], tz1 = inpl ? B.b[2] : whi[2];
+  const int ox = tx0 + ti * sx, oy = ty0 + tj * sy, oz = tz0 + tk * a.zc;
+  if (ox >= (inpl ? B.b[0] : whi[0]) || oy >= (inpl ? B.b[1] : whi[1]) || oz >= tz1) return;
+  int oz1 = oz + a.zc < tz1 ? oz + a.zc : tz1;
+  const bool ghosts = inpl && PRO == PRO_CORRECT;
+  const int zs0 = ghosts ? glo[2] : oz, zs1 = ghosts ? ghi[2] : oz1;  // planes stored
   const long long mm = (long long)gu.m * gu.m;
 
   // steps p0..p1, padded to a multiple of PF: the padding steps only touch
   // planes past the chunk, whose results are never stored
-  const int p0 = oz - NS, p1 = oz1 - 1 + NS;
+  const int p0 = oz - NS, p1 = zs1 - 1 + NS;
   const int nsteps = ((p1 - p0 + 1) + PF - 1) / PF * PF;
 
   const Box Br = seg_box(a.gr, q);
@@ -100,13 +117,14 @@ k_smooth_z(SmoothArgs<T> a) {
   const T* __restrict__ ub = a.uin + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
   const T* __restrict__ cd = PRO == PRO_CORRECT ? a.c + Bc.base : nullptr;
+  const T* __restrict__ cdt = PRO == PRO_CORRECT ? a.ct + Bc.base : nullptr;
   const long long rmm = (long long)a.gr.m * a.gr.m;
   const long long cmm = (long long)a.gc.m * a.gc.m;
 
   // tile columns are numbered row-major over txw x tyw; thread t owns
   // columns t, t + NT, ...
   T U[NS + 2][RY], F[NS + 1][RY];
-  T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY];  // ring of planes in flight
+  T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
   int xr[RY], ys[RY], uo[RY], ci[RY];
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
                     // bits 4-6 boundary faces in x and y
@@ -121,7 +139,9 @@ k_smooth_z(SmoothArgs<T> a) {
     ys[r] = y;
     const bool st = col && x >= wlo[0] && x < whi[0] && y >= wlo[1] && y < whi[1];
     const bool inc = col && x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1];
-    const bool outp = st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H;
+    const bool ing = col && x >= glo[0] && x < ghi[0] && y >= glo[1] && y < ghi[1];
+    const bool outp = inpl ? (inc || (ghosts && ing))
+                           : (st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H);
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4);
@@ -137,7 +157,8 @@ k_smooth_z(SmoothArgs<T> a) {
   // read fetch the first element of the same array and their validity bit
   // masks the value at use -- so loads in flight can be counted exactly.
   unsigned Vu[PF], Vf[PF];
-  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], unsigned& vu, unsigned& vf) {
+  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], T(&qt)[RY], unsigned& vu,
+                   unsigned& vf) {
     const bool zs = p >= wlo[2] && p < whi[2];
     const bool zcin = p >= B.a[2] && p < B.b[2];
     const long long pu = (long long)(p - B.o[2]) * mm;
@@ -152,14 +173,17 @@ k_smooth_z(SmoothArgs<T> a) {
       vu |= (v ? 1u : 0u) << r;
       vf |= (w ? 1u : 0u) << r;
       qu[r] = ub[v ? pu + uo[r] : 0];
-      if (PRO == PRO_CORRECT)
-        qd[r] = cd[v ? pc + ((ys[r] >> 1) - Bc.o[1]) * a.gc.m + ((xr[r] >> 1) - Bc.o[0]) : 0];
+      if (PRO == PRO_CORRECT) {
+        const long long ic = v ? pc + ((ys[r] >> 1) - Bc.o[1]) * a.gc.m + ((xr[r] >> 1) - Bc.o[0]) : 0;
+        qd[r] = cd[ic];
+        qt[r] = cdt[ic];
+      }
       qf[r] = rb[w ? pr + (ys[r] - Br.o[1]) * a.gr.m + (xr[r] - Br.o[0]) : 0];
     }
   };
 
 #pragma unroll
-  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Vu[k], Vf[k]);
+  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Qt[k], Vu[k], Vf[k]);
   for (int pb = p0; pb < p0 + nsteps; pb += PF) {
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -174,11 +198,11 @@ k_smooth_z(SmoothArgs<T> a) {
         for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const T v = PRO == PRO_CORRECT ? Qu[k][r] + Qd[k][r] : Qu[k][r];
+        const T v = PRO == PRO_CORRECT ? Qu[k][r] + (Qd[k][r] - Qt[k][r]) : Qu[k][r];
         U[0][r] = ((Vu[k] >> r) & 1u) ? v : (T)0;
         F[0][r] = ((Vf[k] >> r) & 1u) ? Qf[k][r] : (T)0;
       }
-      fetch(p + PF, Qu[k], Qf[k], Qd[k], Vu[k], Vf[k]);
+      fetch(p + PF, Qu[k], Qf[k], Qd[k], Qt[k], Vu[k], Vf[k]);
       // NS half-sweeps as a wavefront: stage s updates plane p - s
 #pragma unroll
       for (int s = 1; s <= NS; ++s) {
@@ -207,7 +231,7 @@ k_smooth_z(SmoothArgs<T> a) {
       }
       // plane p - NS is final
       const int zo = p - NS;
-      if (zo >= oz && zo < oz1) {
+      if (zo >= zs0 && zo < zs1) {
         const long long pw = (long long)(zo - B.o[2]) * mm;
 #pragma unroll
         for (int r = 0; r < RY; ++r)
@@ -308,11 +332,21 @@ struct BoxArgs {
   Geo gu;
   const T* rhs;
   Geo gr;
-  const T* d;  // coarse increment (correct)
+  const T* d;   // coarse w (correct: the increment is w - t)
+  const T* dt;  // coarse t (correct)
   Geo gc;
   T h2;
   int nu;
 };
+
+// 1 / (6 + nb) for nb = 0..3 boundary faces, without a division (a cell of
+// a level with edge n >= 2 touches at most one wall per dimension)
+template <class T>
+__device__ inline T box_inv_diag(unsigned nb) {
+  const T lo = (nb & 1u) ? (T)(1.0 / 7.0) : (T)(1.0 / 6.0);
+  const T hi = (nb & 1u) ? (T)(1.0 / 9.0) : (T)(1.0 / 8.0);
+  return (nb & 2u) ? hi : lo;
+}
 
 template <class T, int PRO>
 __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
@@ -320,67 +354,103 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   T* bu = reinterpret_cast<T*>(smem_raw);
   const Geo gu = a.gu;
   const int q = blockIdx.x, n = gu.n, m = gu.m, m2 = m * m, mc = m * m2;
+  const int NT = blockDim.x;
   const Box B = seg_box(gu, q), Br = seg_box(a.gr, q), Bc = seg_box(a.gc, q);
   T* __restrict__ ub = a.u + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
 
-  for (int c = threadIdx.x; c < mc; c += blockDim.x) {
-    const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
-    const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
-    T v = 0;
-    if (in_dom(n, x, y, z)) {
-      v = ub[c];
-      if (PRO == PRO_CORRECT) v = v + a.d[at(a.gc, Bc, x >> 1, y >> 1, z >> 1)];
+  // load the box (u, or u + P(d)), four cells per thread in flight
+  for (int base = 0; base < mc; base += 4 * NT) {
+    T v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = base + threadIdx.x + r * NT;
+      v[r] = 0;
+      if (c < mc) {
+        const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
+        const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
+        if (in_dom(n, x, y, z)) {
+          v[r] = ub[c];
+          if (PRO == PRO_CORRECT) {
+            const long long ic = at(a.gc, Bc, x >> 1, y >> 1, z >> 1);
+            v[r] = v[r] + (a.d[ic] - a.dt[ic]);
+          }
+        }
+      }
     }
-    bu[c] = v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = base + threadIdx.x + r * NT;
+      if (c < mc) bu[c] = v[r];
+    }
   }
 
-  // cell pairs of C: pair (xp, y, z) holds x = a0 + 2 xp and x + 1
+  // cell pairs of C: pair (xp, y, z) holds x = a0 + 2 xp and x + 1; the
+  // right-hand side and diagonal inverse of both cells stay in registers
   const int cx = B.b[0] - B.a[0], cy = B.b[1] - B.a[1], cz = B.b[2] - B.a[2];
   const int px = (cx + 1) / 2, np = px * cy * cz;
-  int li[kBoxSlots], gi[kBoxSlots];
+  int li[kBoxSlots];
   unsigned fl[kBoxSlots];  // bit0 parity of the first cell, bit1 second cell exists,
-                           // bits 2-4 / 5-7 boundary faces of the first / second cell
+                           // bits 2-3 / 4-5 boundary faces of the first / second cell
+  T r0[kBoxSlots], r1[kBoxSlots];
   int ns = 0;
 #pragma unroll
   for (int t = 0; t < kBoxSlots; ++t) {
-    const int s = threadIdx.x + t * kBoxThreads;
+    const int s = threadIdx.x + t * NT;
     li[t] = 0;
-    gi[t] = 0;
     fl[t] = 0;
+    r0[t] = r1[t] = 0;
     if (s < np) {
       const int zz = s / (px * cy), yy = (s - zz * px * cy) / px, xp = s - zz * px * cy - yy * px;
       const int x = B.a[0] + 2 * xp, y = B.a[1] + yy, z = B.a[2] + zz;
       li[t] = ((z - B.o[2]) * m + (y - B.o[1])) * m + (x - B.o[0]);
-      gi[t] = (int)(((long long)(z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]));
+      const long long gi = ((long long)(z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]);
+      const bool two = x + 1 < B.b[0];
       const int byz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
-      const int nb0 = byz + (x == 0) + (x == n - 1);
-      const int nb1 = byz + (x + 1 == 0) + (x + 1 == n - 1);
-      fl[t] = ((x + y + z) & 1) | ((x + 1 < B.b[0]) ? 2u : 0u) | (nb0 << 2) | (nb1 << 5);
+      const unsigned nb0 = byz + (x == 0) + (x == n - 1), nb1 = byz + (x + 1 == n - 1);
+      fl[t] = ((x + y + z) & 1) | (two ? 2u : 0u) | (nb0 << 2) | (nb1 << 4);
+      r0[t] = rb[gi];
+      if (two) r1[t] = rb[gi + 1];
       ns = t + 1;
     }
   }
   __syncthreads();
 
+  // red-black sweeps: per group of slots, all loads, then the stores (cells
+  // of one colour read only the other colour).  The slot flags pass through
+  // an empty asm so that the per-colour selections are formed in the sweep
+  // instead of being hoisted for both colours (which exhausts registers).
+  constexpr int G = 8;  // slots per group: bounds the loads in flight
+  const T h2 = a.h2;
   for (int it = 0; it < a.nu; ++it)
     for (int col = 0; col < 2; ++col) {
 #pragma unroll
-      for (int t = 0; t < kBoxSlots; ++t) {
-        if (t < ns) {
-          const int off = (fl[t] ^ col) & 1;  // which cell of the pair has colour col
-          if (!off || (fl[t] & 2u)) {
+      for (int g0 = 0; g0 < kBoxSlots; g0 += G) {
+        T nv[G];
+        int lw[G];
+#pragma unroll
+        for (int t = g0; t < g0 + G; ++t) {
+          nv[t - g0] = 0;
+          lw[t - g0] = -1;
+          if (t < ns) {
+            unsigned f = fl[t] ^ (unsigned)col;
+            asm volatile("" : "+v"(f));
+            const int off = f & 1;  // which cell of the pair has colour col
             const int l = li[t] + off;
-            const T s = bu[l - 1] + bu[l + 1] + bu[l - m] + bu[l + m] + bu[l - m2] + bu[l + m2];
-            const int nb = off ? (fl[t] >> 5) & 7 : (fl[t] >> 2) & 7;
-            bu[l] = (s - a.h2 * rb[gi[t] + off]) / (T)(6 + nb);
+            const T s = ((bu[l - 1] + bu[l + 1]) + (bu[l - m] + bu[l + m])) + (bu[l - m2] + bu[l + m2]);
+            nv[t - g0] = (s - h2 * (off ? r1[t] : r0[t])) * box_inv_diag<T>((f >> (off ? 4 : 2)) & 3u);
+            if (!off || (f & 2u)) lw[t - g0] = l;
           }
         }
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+          if (lw[t] >= 0) bu[lw[t]] = nv[t];
       }
       __syncthreads();
     }
 
   // write back: the compute region, and the ghosts when the prologue changed them
-  for (int c = threadIdx.x; c < mc; c += blockDim.x) {
+  for (int c = threadIdx.x; c < mc; c += NT) {
     const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
     const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
     if (!in_dom(n, x, y, z)) continue;

@@ -152,24 +152,10 @@ __global__ void k_coarse_rhs(const T* __restrict__ uc, T* __restrict__ rc, T* __
   rc[id] = (T)(r + Lu);
 }
 
-// d = w - t on every stored cell of a coarse level (written over t): the
-// increment the coarse-grid correction prolongs (Fig. 1 and Fig. 6)
+// u += P(w - t) on C and the GSR ghosts (every stored cell inside the domain)
 template <class T>
-__global__ void k_diff(const T* __restrict__ w, T* __restrict__ t, Geo gc) {
-  int q = blockIdx.y;
-  Box Bc = seg_box(gc, q);
-  int me = gc.m;
-  int x, y, z;
-  if (!cell_of((long long)blockIdx.x * blockDim.x + threadIdx.x, me, me, me, x, y, z)) return;
-  int i = Bc.o[0] + x, j = Bc.o[1] + y, k = Bc.o[2] + z;
-  if (!in_dom(gc.n, i, j, k)) return;
-  long long id = at(gc, Bc, i, j, k);
-  t[id] = w[id] - t[id];
-}
-
-// u += P(d) on C and the GSR ghosts (every stored cell inside the domain)
-template <class T>
-__global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ d, Geo gc) {
+__global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ w,
+                          const T* __restrict__ t, Geo gc) {
   int q = blockIdx.y;
   Box B = seg_box(gu, q), Bc = seg_box(gc, q);
   int me = gu.m;
@@ -179,7 +165,7 @@ __global__ void k_correct(T* __restrict__ u, Geo gu, const T* __restrict__ d, Ge
   if (!in_dom(gu.n, i, j, k)) return;
   long long pc = at(gc, Bc, i >> 1, j >> 1, k >> 1);
   long long id = at(gu, B, i, j, k);
-  u[id] = (T)(u[id] + d[pc]);
+  u[id] = (T)(u[id] + (w[pc] - t[pc]));
 }
 
 // FMG interpolation onto C and the GSR ghosts

@@ -116,10 +116,11 @@ def test_schedule_model_byte_counts():
     _, r, _ = fmg.schedule_model(256, levels=8, sr_levels=3, segments=8, buffers=(2, 4, 6),
                                  precision="fp32_refined")
     N3 = 256 ** 3
-    # segmental refinement recomputes buffer cells, the refined solve runs
-    # three FP32 solves plus FP64 residuals
+    # segmental refinement recomputes buffer cells (1.4x to 12x the genuine
+    # cells on the SR levels; its finest level takes two sweeps per pass), the
+    # refined solve runs three FP32 solves plus FP64 residuals
     assert 60 < g / N3 < 300
-    assert 1.5 < s / g < 3.5
+    assert 1.1 < s / g < 3.5
     assert r > s
 
 
