@@ -148,6 +148,21 @@ typedef struct {
 
 int32_t fmg_schedule_model(int32_t N, const fmg_params *p, fmg_schedule_stat *out);
 
+/*
+ * Norms (the quantities Sec. 7 reports in Figs. 8 and 10), by wavefront
+ * reduction on the device.  f, u, v: device arrays of N^3 doubles (layout as
+ * above); out: HOST array of 2 doubles.  Both calls allocate a small temporary
+ * device buffer and synchronize `stream` before returning.
+ *   fmg_residual_norms: r = f - L_h u (7-point operator of Eq. 2);
+ *   fmg_diff_norms:     r = u - v;
+ *   out[0] = max_c |r_c|,  out[1] = sqrt(h^3 sum_c r_c^2)  (h = 1/N: the L2
+ *   norm of the cellwise-constant function on the unit cube).
+ * FMG_EINVAL for null pointers, N < 1 or f == u; FMG_ENOMEM / FMG_EHIP.
+ */
+int32_t fmg_residual_norms(const double *f, const double *u, int32_t N, double *out,
+                           void *stream);
+int32_t fmg_diff_norms(const double *u, const double *v, int32_t N, double *out, void *stream);
+
 /* Message of the last non-OK status returned on this thread ("" if none). */
 const char *fmg_last_error(void);
 

@@ -25,11 +25,11 @@ def eigenvalue(k, N):
 def dst_solve(f):
     """u = L_h^{-1} f via DST-II along every axis (any N)."""
     N = f.shape[0]
-    F = scipy.fft.dstn(f, type=2, norm="ortho")
+    F = scipy.fft.dstn(f, type=2, norm="ortho", workers=-1)
     k = np.arange(1, N + 1, dtype=np.float64)
     s = np.sin(k * math.pi / (2.0 * N)) ** 2
     lam = -(4.0 * N * N) * (s[:, None, None] + s[None, :, None] + s[None, None, :])
-    return scipy.fft.idstn(F / lam, type=2, norm="ortho")
+    return scipy.fft.idstn(F / lam, type=2, norm="ortho", workers=-1)
 
 
 def sine_discrete(N):

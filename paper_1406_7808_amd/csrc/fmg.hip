@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -27,6 +28,7 @@
 #include "kernels_coarse.hpp"
 #include "kernels_descend.hpp"
 #include "kernels_fused.hpp"
+#include "kernels_norms.hpp"
 #include "kernels_simple.hpp"
 
 using namespace fmg;
@@ -217,6 +219,7 @@ struct fmg_plan {
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
   int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
   bool seg_inplace = true;    // segment levels: in place, one workgroup per segment
+  std::set<const void*> lds_attr;  // kernels already allowed the whole LDS
   long long target_blocks = 1024;  // workgroups a fused launch aims for
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
@@ -320,7 +323,9 @@ static bool nonnull(const DescArgs<X>& a) {
 }
 template <class X>
 static bool nonnull(const BoxArgs<X>& a) {
-  return a.u && a.rhs && a.d && a.dt && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc);
+  return a.u && a.rhs && a.d && a.dt && geo_ok(a.gu) && geo_ok(a.gr) && geo_ok(a.gc) &&
+         (!a.fas || (a.rhsw && a.t && geo_ok(a.gf))) &&
+         (a.rmode < 0 || (a.uc && a.rc && geo_ok(a.gcr) && a.rmode <= 1));
 }
 template <class X>
 static bool nonnull(const CoarseArgs<X>& a) {
@@ -504,17 +509,24 @@ struct Exec {
     return cube(G.m) * (long long)sizeof(T) <= P->lds_max && pairs <= kBoxSlots * kBoxThreads;
   }
 
+  // allow a kernel the device's whole LDS per workgroup (once per plan, so
+  // once per device)
+  void allow_lds(const void* fn, int bytes) {
+    if (dry || P->lds_attr.count(fn)) return;
+    hipcheck(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes),
+             "hipFuncSetAttribute");
+    P->lds_attr.insert(fn);
+  }
+
+  // fas: form the FAS right-hand side in the prologue (see BoxArgs); rmode >= 0:
+  // residual and restriction in the epilogue (0: to F of the coarse segment,
+  // 1: owner computes into the global transition level)
   template <int PRO>
-  void smooth_box_pro(int l, const T* rhs, Geo gr, int nu, const T* d, const T* dt, Geo gc) {
+  void smooth_box_pro(int l, const T* rhs, Geo gr, int nu, const T* d, const T* dt, Geo gc,
+                      int fas, int rmode) {
     const Geo& G = H.geo[l];
     size_t shm = (size_t)cube(G.m) * sizeof(T);
-    static bool attr_set = false;  // once per instantiation: allow the device maximum
-    if (!dry && !attr_set) {
-      hipcheck(hipFuncSetAttribute((const void*)k_smooth_box<T, PRO>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max),
-               "hipFuncSetAttribute");
-      attr_set = true;
-    }
+    allow_lds((const void*)k_smooth_box<T, PRO>, P->lds_max);
     BoxArgs<T> a{};
     a.u = H.u[l];
     a.gu = G;
@@ -526,17 +538,34 @@ struct Exec {
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
     a.nu = nu;
+    a.fas = PRO == PRO_LOAD ? fas : 0;
+    a.rhsw = H.rhs[l];
+    a.t = H.t[l];
+    a.gf = H.geo[l + 1 < P->L ? l + 1 : l];
+    a.rmode = PRO == PRO_LOAD ? rmode : -1;
+    a.uc = H.u[l - 1];
+    a.rc = H.rhs[l - 1];
+    a.gcr = H.geo[l - 1];
+    if (a.fas && (rhs != H.rhs[l] || l + 1 >= P->L))
+      throw hip_error("internal: FAS prologue needs the level's own right-hand side");
     double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
-    run_shm(PRO == PRO_CORRECT ? "k_smooth_box<correct>" : "k_smooth_box<load>",
-            sizeof(T) * (2.0 + rd) * c_cells(G), dim3(nseg(l)),
-            dim3(kBoxThreads), shm, k_smooth_box<T, PRO>, a);
+    double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
+    if (a.fas) bytes += sizeof(T) * (c_cells(G) + st_cells(G));  // rhs and t written
+    if (a.rmode >= 0)
+      bytes += sizeof(T) * 2.0 * (a.rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
+    run_shm(PRO == PRO_CORRECT ? "k_smooth_box<correct>" : "k_smooth_box<load>", bytes,
+            dim3(nseg(l)), dim3(kBoxThreads), shm, k_smooth_box<T, PRO>, a);
   }
 
   void smooth_box(int l, const T* rhs, Geo gr, int nu, int pro, const T* d, const T* dt,
-                  Geo gc) {
-    if (pro == PRO_CORRECT) smooth_box_pro<PRO_CORRECT>(l, rhs, gr, nu, d, dt, gc);
-    else smooth_box_pro<PRO_LOAD>(l, rhs, gr, nu, d, dt, gc);
+                  Geo gc, int fas, int rmode) {
+    if (pro == PRO_CORRECT) smooth_box_pro<PRO_CORRECT>(l, rhs, gr, nu, d, dt, gc, 0, -1);
+    else smooth_box_pro<PRO_LOAD>(l, rhs, gr, nu, d, dt, gc, fas, rmode);
   }
+
+  // does the first smoothing pass of SR level l take the box path (and so
+  // can form the FAS right-hand side and the restriction itself)?
+  bool box_pass(int l, int nu) const { return nu > 0 && P->fused && box_fits(l); }
 
   // FMG interpolation onto the current copy of level l (streaming kernel)
   void interp(int l) {
@@ -552,7 +581,9 @@ struct Exec {
 
   // prologue (none, FMG interpolation from level l-1, or the coarse-grid
   // correction from level l-1) followed by nu red-black sweeps on level l
-  void smooth(int l, const T* rhs, Geo gr, int nu, int pro = PRO_LOAD) {
+  // returns true when the pass also restricted (rmode >= 0 on the box path)
+  bool smooth(int l, const T* rhs, Geo gr, int nu, int pro = PRO_LOAD, int fas = 0,
+              int rmode = -1) {
     lvl = l;
     const Geo& G = H.geo[l];
     const Geo& Gc = H.geo[l > 0 ? l - 1 : 0];
@@ -565,15 +596,16 @@ struct Exec {
     }
     int st = 2 * nu;
     if (st > 0 && P->fused && box_fits(l)) {
-      smooth_box(l, rhs, gr, nu, pro, d, dt, Gc);
-      return;
+      smooth_box(l, rhs, gr, nu, pro, d, dt, Gc, fas, rmode);
+      return rmode >= 0 && pro != PRO_CORRECT;
     }
+    if (fas) throw hip_error("internal: FAS prologue requested off the box path");
     if (st == 0 || !P->fused) {
       if (pro == PRO_CORRECT)
         run("k_correct", sizeof(T) * 2.25 * st_cells(G), grid_for(cube(G.m), nseg(l)),
             dim3(kBlock), k_correct<T>, H.u[l], G, d, dt, Gc);
       smooth_simple(l, rhs, gr, nu);
-      return;
+      return false;
     }
     bool first = true;
     const bool inpl = seg_inplace(l);
@@ -586,6 +618,7 @@ struct Exec {
       st -= ns;
       first = false;
     }
+    return false;
   }
 
   // the persistent coarse-level kernel: FMG stages 0..top (mode 0) or one
@@ -613,14 +646,8 @@ struct Exec {
     a.alpha = P->alpha;
     size_t shm = sizeof(T) * (size_t)coarse_lds_elems(a.n, top, mode);
     if ((long long)shm + 1024 > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
-    static bool attr_set = false;  // once per instantiation: allow the device maximum
-    if (!dry && !attr_set) {
-      // the kernel also holds a small static LDS block (level offsets)
-      hipcheck(hipFuncSetAttribute((const void*)k_coarse<T>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, P->lds_max - 1024),
-               "hipFuncSetAttribute");
-      attr_set = true;
-    }
+    // the kernel also holds a small static LDS block (level offsets)
+    allow_lds((const void*)k_coarse<T>, P->lds_max - 1024);
     run_shm(mode == 0 ? "k_coarse<fmg>" : "k_coarse<vcycle>", bytes, dim3(1),
             dim3(kCoarseThreads), shm, k_coarse<T>, a);
   }
@@ -629,7 +656,11 @@ struct Exec {
 
   // restriction of u and of the residual onto the coarse target cells, then
   // the coarse right-hand side and t
-  void descend(int l, const T* rhs, Geo gr, int mode, int whole_f) {
+  // restriction of u and of the residual onto the coarse target cells
+  // (skipped when the smoothing pass did it), then the coarse right-hand side
+  // and t (skipped when the coarse level's first pass forms them)
+  void descend(int l, const T* rhs, Geo gr, int mode, int whole_f, bool restricted = false,
+               bool rhs_deferred = false) {
     lvl = l;
     const Geo& G = H.geo[l];
     const Geo& Gc = H.geo[l - 1];
@@ -637,14 +668,17 @@ struct Exec {
     int ce = mode == 0 ? cext(l) / 2 : Gc.n / P->S;
     double coarse = mode == 0 ? c_cells(G) / 8.0 : cube(Gc.n);
     double bytes = sizeof(T) * (16.0 * coarse + 2.0 * coarse);
-    // the streaming pass on large targets; small ones are latency bound and
-    // take the one-thread-per-coarse-cell kernel
-    if (P->fused && cube(ce) * ns > 300000) {
+    if (restricted) {
+      // done in the smoothing pass's epilogue
+    } else if (P->fused && cube(ce) * ns > 300000) {
+      // the streaming pass on large targets; small ones are latency bound and
+      // take the one-thread-per-coarse-cell kernel
       descend_z(l, rhs, gr, mode, ce, bytes);
     } else {
       run("k_resid_restrict", bytes, grid_for(cube(ce), ns), dim3(kBlock), k_resid_restrict<T>,
           (const T*)H.u[l], G, rhs, gr, H.u[l - 1], H.rhs[l - 1], Gc, mode, ce);
     }
+    if (rhs_deferred) return;
     int nsc = mode == 0 ? ns : 1;
     run("k_coarse_rhs", 4.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nsc), dim3(kBlock),
         k_coarse_rhs<T>, (const T*)H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, whole_f);
@@ -711,17 +745,23 @@ struct Exec {
   }
 
   // SR V-cycle on segment level l inside the FMG stage whose top level is top
-  // (Fig. 6); the top level's rhs is the global f_top read over C
-  void vcycle_sr(int l, int top, bool presmoothed = false) {
+  // (Fig. 6); the top level's rhs is the global f_top read over C.
+  // presmoothed: S^nu1 was applied by the caller (and restricted tells
+  // whether that pass also restricted); fas: this level was just restricted
+  // into and its first pass forms the FAS right-hand side and t.
+  void vcycle_sr(int l, int top, bool presmoothed = false, bool restricted = false,
+                 bool fas = false) {
     const Geo& G = H.geo[l];
     const T* rhs = (l == top) ? H.f[l] : H.rhs[l];
     Geo gr = (l == top) ? global_geo(G.n) : G;
-    if (!presmoothed) smooth(l, rhs, gr, P->nu1);
+    const int rmode = (l - 1 > P->T) ? 0 : 1;
+    if (!presmoothed) restricted = smooth(l, rhs, gr, P->nu1, PRO_LOAD, fas ? 1 : 0, rmode);
     if (l - 1 > P->T) {
-      descend(l, rhs, gr, 0, 0);
-      vcycle_sr(l - 1, top);
+      const bool next_fas = box_pass(l - 1, P->nu1);
+      descend(l, rhs, gr, 0, 0, restricted, next_fas);
+      vcycle_sr(l - 1, top, false, false, next_fas);
     } else {
-      descend(l, rhs, gr, 1, 1);  // owner-computes transition restriction
+      descend(l, rhs, gr, 1, 1, restricted);  // owner-computes transition restriction
       vcycle_global(l - 1, H.rhs[l - 1]);
     }
     smooth(l, rhs, gr, P->nu2, PRO_CORRECT);
@@ -745,11 +785,14 @@ struct Exec {
     for (int l = P->Lc + 1; l < L; ++l) {
       const Geo& G = H.geo[l];
       // Pi, S^alpha and the V-cycle's S^nu1 form one fused pass
-      smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP);
-      if (l <= P->T)
+      if (l <= P->T) {
+        smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP);
         vcycle_global(l, H.f[l], true);
-      else
-        vcycle_sr(l, l, true);
+      } else {
+        const int rmode = (l - 1 > P->T) ? 0 : 1;
+        bool r = smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP, 0, rmode);
+        vcycle_sr(l, l, true, r);
+      }
     }
     if (P->K > 0) {
       const Geo& G = H.geo[L - 1];
@@ -1030,6 +1073,49 @@ int32_t fmg_plan_profile_read(fmg_plan* P, fmg_kernel_stat* out, int32_t cap, in
   *count = (int32_t)agg.size();
   for (int32_t i = 0; i < cap && i < (int32_t)agg.size(); ++i) out[i] = agg[i];
   return FMG_OK;
+}
+
+// a10: norms of f - L u (mode 0) or u - v (mode 1); partial results in a
+// temporary device buffer, the two norms copied to the host
+static int32_t norms(const double* a, const double* b, int32_t n, int mode, double* out,
+                     void* stream) {
+  if (!a || !b || !out || n < 1) return fail(FMG_EINVAL, "bad arguments");
+  if (a == b && mode == 0) return fail(FMG_EINVAL, "f and u must not be the same array");
+  hipStream_t st = (hipStream_t)stream;
+  const long long cnt = cube(n);
+  long long nb = (cnt + kNormThreads - 1) / kNormThreads;
+  if (nb > 1024) nb = 1024;
+  double* part = nullptr;
+  if (hipMalloc(&part, sizeof(double) * (size_t)(2 * nb + 2)) != hipSuccess)
+    return fail(FMG_ENOMEM, "hipMalloc failed");
+  int32_t ret = FMG_OK;
+  double res[2] = {0.0, 0.0};
+  hipLaunchKernelGGL(k_norms, dim3((unsigned)nb), dim3(kNormThreads), 0, st, a, b, (int)n, mode,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kNormThreads), 0, st, (const double*)part,
+                       (int)nb, (int)n, part + 2 * nb);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(res, part + 2 * nb, sizeof res, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) ret = fail(FMG_EHIP, hipGetErrorString(e));
+  (void)hipFree(part);
+  if (ret == FMG_OK) {
+    out[0] = res[0];
+    out[1] = res[1];
+  }
+  return ret;
+}
+
+int32_t fmg_residual_norms(const double* f, const double* u, int32_t N, double* out,
+                           void* stream) {
+  return norms(f, u, N, 0, out, stream);
+}
+
+int32_t fmg_diff_norms(const double* u, const double* v, int32_t N, double* out, void* stream) {
+  return norms(u, v, N, 1, out, stream);
 }
 
 int32_t fmg_op_apply(const double* u, int32_t n, double* out, void* stream) {

@@ -337,6 +337,21 @@ struct BoxArgs {
   Geo gc;
   T h2;
   int nu;
+  // FAS prologue (fas > 0, load prologue only): the level was just restricted
+  // into; rhs holds R res on F.  The kernel forms rhs = R res + L u on F and
+  // L u on C \ F (Fig. 6; fas == 2: F is the whole region), writes it back
+  // over rhs, and writes t = the loaded box.
+  int fas;
+  T* rhsw;  // = rhs, writable
+  T* t;
+  Geo gf;   // the finer level: F = its compute region / 2
+  // residual-restriction epilogue (rmode >= 0): uc = R u and rc = R (rhs -
+  // L u) on the coarse target (rmode 0: C / 2 of the segment; 1: the genuine
+  // coarse cells, in the global coarse level)
+  int rmode;
+  T* uc;
+  T* rc;
+  Geo gcr;
 };
 
 // 1 / (6 + nb) for nb = 0..3 boundary faces, without a division (a cell of
@@ -358,8 +373,10 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   const Box B = seg_box(gu, q), Br = seg_box(a.gr, q), Bc = seg_box(a.gc, q);
   T* __restrict__ ub = a.u + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
+  const bool fas = PRO == PRO_LOAD && a.fas > 0;
 
-  // load the box (u, or u + P(d)), four cells per thread in flight
+  // load the box (u, or u + P(d)), four cells per thread in flight; the FAS
+  // prologue also stores the loaded box as t
   for (int base = 0; base < mc; base += 4 * NT) {
     T v[4];
 #pragma unroll
@@ -381,7 +398,10 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = base + threadIdx.x + r * NT;
-      if (c < mc) bu[c] = v[r];
+      if (c < mc) {
+        bu[c] = v[r];
+        if (fas) a.t[B.base + c] = v[r];
+      }
     }
   }
 
@@ -389,32 +409,75 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   // right-hand side and diagonal inverse of both cells stay in registers
   const int cx = B.b[0] - B.a[0], cy = B.b[1] - B.a[1], cz = B.b[2] - B.a[2];
   const int px = (cx + 1) / 2, np = px * cy * cz;
-  int li[kBoxSlots];
+  int li[kBoxSlots], gi[kBoxSlots];
   unsigned fl[kBoxSlots];  // bit0 parity of the first cell, bit1 second cell exists,
-                           // bits 2-3 / 4-5 boundary faces of the first / second cell
+                           // bits 2-3 / 4-5 boundary faces of the first / second cell,
+                           // bits 6 / 7 first / second cell in F (FAS prologue)
   T r0[kBoxSlots], r1[kBoxSlots];
   int ns = 0;
+  int flo[3] = {0, 0, 0}, fhi[3] = {n, n, n};
+  if (fas && a.fas == 1) {
+    const Box Bf = seg_box(a.gf, q);
+    for (int d = 0; d < 3; ++d) {
+      flo[d] = Bf.a[d] / 2;
+      fhi[d] = Bf.b[d] / 2;
+    }
+  }
 #pragma unroll
   for (int t = 0; t < kBoxSlots; ++t) {
     const int s = threadIdx.x + t * NT;
     li[t] = 0;
+    gi[t] = 0;
     fl[t] = 0;
     r0[t] = r1[t] = 0;
     if (s < np) {
       const int zz = s / (px * cy), yy = (s - zz * px * cy) / px, xp = s - zz * px * cy - yy * px;
       const int x = B.a[0] + 2 * xp, y = B.a[1] + yy, z = B.a[2] + zz;
       li[t] = ((z - B.o[2]) * m + (y - B.o[1])) * m + (x - B.o[0]);
-      const long long gi = ((long long)(z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]);
+      gi[t] = ((z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]);
       const bool two = x + 1 < B.b[0];
       const int byz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
       const unsigned nb0 = byz + (x == 0) + (x == n - 1), nb1 = byz + (x + 1 == n - 1);
-      fl[t] = ((x + y + z) & 1) | (two ? 2u : 0u) | (nb0 << 2) | (nb1 << 4);
-      r0[t] = rb[gi];
-      if (two) r1[t] = rb[gi + 1];
+      const bool fyz = y >= flo[1] && y < fhi[1] && z >= flo[2] && z < fhi[2];
+      const bool f0 = fyz && x >= flo[0] && x < fhi[0];
+      const bool f1 = fyz && x + 1 >= flo[0] && x + 1 < fhi[0];
+      fl[t] = ((x + y + z) & 1) | (two ? 2u : 0u) | (nb0 << 2) | (nb1 << 4) | (f0 ? 64u : 0u) |
+              (f1 ? 128u : 0u);
+      r0[t] = rb[gi[t]];
+      if (two) r1[t] = rb[gi[t] + 1];
       ns = t + 1;
     }
   }
   __syncthreads();
+
+  const double s2 = (double)n * (double)n;
+  // L u of the cell at LDS index l with nb boundary faces (Eq. 2, in FP64)
+  auto lap = [&](int l, unsigned nb) -> double {
+    const double s = (((double)bu[l - 1] + (double)bu[l + 1]) +
+                      ((double)bu[l - m] + (double)bu[l + m])) +
+                     ((double)bu[l - m2] + (double)bu[l + m2]);
+    return (s - (double)(6 + nb) * (double)bu[l]) * s2;
+  };
+
+  if (fas) {  // rhs = (R res on F, else 0) + L u, kept in registers and stored
+#pragma unroll
+    for (int t = 0; t < kBoxSlots; ++t) {
+      if (t < ns) {
+        unsigned f = fl[t];
+        asm volatile("" : "+v"(f));
+        const double l0 = lap(li[t], (f >> 2) & 3u);
+        r0[t] = (T)(((f & 64u) ? (double)r0[t] : 0.0) + l0);
+        a.rhsw[Br.base + gi[t]] = r0[t];
+        if (f & 2u) {
+          const double l1 = lap(li[t] + 1, (f >> 4) & 3u);
+          r1[t] = (T)(((f & 128u) ? (double)r1[t] : 0.0) + l1);
+          a.rhsw[Br.base + gi[t] + 1] = r1[t];
+        }
+      }
+    }
+  }
+
+  if (fas) __syncthreads();  // the prologue read u before the sweeps write it
 
   // red-black sweeps: per group of slots, all loads, then the stores (cells
   // of one colour read only the other colour).  The slot flags pass through
@@ -449,6 +512,20 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       __syncthreads();
     }
 
+  // residuals of the own cells (kept over the right-hand side registers)
+  const bool epi = PRO == PRO_LOAD && a.rmode >= 0;
+  if (epi) {
+#pragma unroll
+    for (int t = 0; t < kBoxSlots; ++t) {
+      if (t < ns) {
+        unsigned f = fl[t];
+        asm volatile("" : "+v"(f));
+        r0[t] = (T)((double)r0[t] - lap(li[t], (f >> 2) & 3u));
+        if (f & 2u) r1[t] = (T)((double)r1[t] - lap(li[t] + 1, (f >> 4) & 3u));
+      }
+    }
+  }
+
   // write back: the compute region, and the ghosts when the prologue changed them
   for (int c = threadIdx.x; c < mc; c += NT) {
     const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
@@ -457,6 +534,55 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
     const bool inC = x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1] && z >= B.a[2] &&
                      z < B.b[2];
     if (inC || PRO == PRO_CORRECT) ub[c] = bu[c];
+  }
+  if (!epi) return;
+
+  // epilogue: restriction of u, then of the residuals (written over u in LDS)
+  int lo[3], hi[3];
+  if (a.rmode == 0) {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = B.a[d] / 2;
+      hi[d] = B.b[d] / 2;
+    }
+  } else {
+    const int S = gu.S, e = a.gcr.n / S;
+    const int p[3] = {q % S, (q / S) % S, q / (S * S)};
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = p[d] * e;
+      hi[d] = (p[d] + 1) * e;
+    }
+  }
+  const Box Bo = seg_box(a.gcr, q);
+  const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ncc = ex * ey * (hi[2] - lo[2]);
+  auto child0 = [&](int cc, long long& id) -> int {  // LDS index of the (0,0,0) child
+    const int K = cc / (ex * ey), J = (cc - K * ex * ey) / ex, I = cc - K * ex * ey - J * ex;
+    id = at(a.gcr, Bo, lo[0] + I, lo[1] + J, lo[2] + K);
+    return ((2 * (lo[2] + K) - B.o[2]) * m + (2 * (lo[1] + J) - B.o[1])) * m +
+           (2 * (lo[0] + I) - B.o[0]);
+  };
+  auto sum8 = [&](int l) -> double {
+    return ((((double)bu[l] + (double)bu[l + 1]) + ((double)bu[l + m] + (double)bu[l + m + 1])) +
+            (((double)bu[l + m2] + (double)bu[l + m2 + 1]) +
+             ((double)bu[l + m2 + m] + (double)bu[l + m2 + m + 1])));
+  };
+  for (int cc = threadIdx.x; cc < ncc; cc += NT) {
+    long long id;
+    const int l = child0(cc, id);
+    a.uc[id] = (T)(sum8(l) / 8.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kBoxSlots; ++t) {
+    if (t < ns) {
+      bu[li[t]] = r0[t];
+      if (fl[t] & 2u) bu[li[t] + 1] = r1[t];
+    }
+  }
+  __syncthreads();
+  for (int cc = threadIdx.x; cc < ncc; cc += NT) {
+    long long id;
+    const int l = child0(cc, id);
+    a.rc[id] = (T)(sum8(l) / 8.0);
   }
 }
 

@@ -49,8 +49,8 @@ class _KernelStat(ctypes.Structure):
 _lib = None
 SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_destroy",
            "fmg_solve", "fmg_plan_workspace_bytes", "fmg_plan_profile", "fmg_plan_profile_read", "fmg_schedule_model",
-           "fmg_last_error", "fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict",
-           "fmg_op_interp"]
+           "fmg_last_error", "fmg_residual_norms", "fmg_diff_norms", "fmg_op_apply",
+           "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
 
 
 def lib():
@@ -83,11 +83,15 @@ def lib():
     L.fmg_schedule_model.restype = i32
     L.fmg_last_error.argtypes = []
     L.fmg_last_error.restype = ctypes.c_char_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.fmg_residual_norms.argtypes = [vp, vp, i32, dp, vp]
+    L.fmg_diff_norms.argtypes = [vp, vp, i32, dp, vp]
     L.fmg_op_apply.argtypes = [vp, i32, vp, vp]
     L.fmg_op_smooth.argtypes = [vp, vp, i32, i32, vp]
     L.fmg_op_restrict.argtypes = [vp, i32, vp, vp]
     L.fmg_op_interp.argtypes = [vp, i32, vp, vp]
-    for name in ("fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"):
+    for name in ("fmg_residual_norms", "fmg_diff_norms", "fmg_op_apply", "fmg_op_smooth",
+                 "fmg_op_restrict", "fmg_op_interp"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -196,6 +200,22 @@ def solve(f, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), prec
     p, keep = make_params(levels, sr_levels, segments, buffers, sweeps, precision, refine_iters)
     _check(lib().fmg_solve(_dev(f, N), N, ctypes.byref(p), _dev(u, N), _stream(None)))
     return u
+
+
+def residual_norms(f, u, stream=None):
+    """(max |f - L u|, sqrt(h^3 sum (f - L u)^2)) over the N^3 grid."""
+    N = f.shape[0]
+    out = (ctypes.c_double * 2)()
+    _check(lib().fmg_residual_norms(_dev(f, N), _dev(u, N), N, out, _stream(stream)))
+    return out[0], out[1]
+
+
+def diff_norms(u, v, stream=None):
+    """(max |u - v|, sqrt(h^3 sum (u - v)^2)) over the N^3 grid."""
+    N = u.shape[0]
+    out = (ctypes.c_double * 2)()
+    _check(lib().fmg_diff_norms(_dev(u, N), _dev(v, N), N, out, _stream(stream)))
+    return out[0], out[1]
 
 
 def op_apply(u):
