@@ -345,6 +345,13 @@ struct Exec {
   hipStream_t s;
   bool dry = false;  // walk the schedule without launching (buffer bookkeeping)
   int lvl = -1;      // level of the launches being issued (profile label)
+  // the solve's final pass may write the genuine cells to fin_out (added when
+  // fin_acc) itself; fin_done records that it did
+  double* want_out = nullptr;  // where this solve's genuine cells go (K > 0)
+  int want_acc = 0;
+  double* fin_out = nullptr;
+  int fin_acc = 0;
+  bool fin_done = false;
 
   int nseg(int l) const { return l > P->T ? P->S * P->S * P->S : 1; }
 
@@ -412,7 +419,8 @@ struct Exec {
   // one temporally blocked launch of NS half-sweeps with prologue PRO; RY
   // columns per thread; inpl: one workgroup per segment, updated in place
   template <int NS, int RY, int PRO>
-  void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl) {
+  void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl,
+                double* out = nullptr, int outmode = 0) {
     constexpr int NT = 1024, NC = NT * RY;
     constexpr int WPE = (NS <= 2 && (RY == 1 || sizeof(T) == 4)) ? 8 : 4;
     const Geo& G = H.geo[l];
@@ -428,6 +436,9 @@ struct Exec {
     a.ct = ct;
     a.gc = gc;
     a.inplace = inpl ? 1 : 0;
+    if (outmode && (!inpl || !out)) throw hip_error("internal: output epilogue needs an in-place pass");
+    a.out = out;
+    a.outmode = outmode;
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
     int ns = nseg(l);
@@ -477,19 +488,21 @@ struct Exec {
     int per = (nt + a.nxcd - 1) / a.nxcd;
     double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
+    if (outmode)  // u is not stored; the genuine cells go out in FP64 (read too when added)
+      bytes += (8.0 * outmode - sizeof(T)) * cube(P->N) - sizeof(T) * c_cells(G);
     run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>", bytes,
         dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE>, a);
   }
 
   template <int PRO>
   void smooth_z_ns(int ns, bool inpl, int l, const T* rhs, Geo gr, const T* c, const T* ct,
-                   Geo gc) {
+                   Geo gc, double* out = nullptr, int outmode = 0) {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
     if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
-    else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true);
-    else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl);
+    else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
+    else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
   }
 
   // can level l's segments be smoothed in place, one workgroup each, with
@@ -613,8 +626,16 @@ struct Exec {
     while (st > 0) {
       int ns = st >= mx ? mx : st;
       int pr = first ? pro : PRO_LOAD;
-      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc);
-      else smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc);
+      // the solve's last pass may deliver the genuine cells itself
+      double* out = nullptr;
+      int om = 0;
+      if (fin_out && inpl && st == ns && l == P->L - 1) {
+        out = fin_out;
+        om = fin_acc ? 2 : 1;
+        fin_done = true;
+      }
+      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+      else smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       st -= ns;
       first = false;
     }
@@ -764,7 +785,12 @@ struct Exec {
       descend(l, rhs, gr, 1, 1, restricted);  // owner-computes transition restriction
       vcycle_global(l - 1, H.rhs[l - 1]);
     }
+    if (l == P->L - 1) {  // the solve's last pass: deliver the genuine cells directly
+      fin_out = want_out;
+      fin_acc = want_acc;
+    }
     smooth(l, rhs, gr, P->nu2, PRO_CORRECT);
+    fin_out = nullptr;
   }
 
   // one FMG solve: ftop is the finest right-hand side (global N^3 of T);
@@ -780,6 +806,9 @@ struct Exec {
       run("k_restrict_global", sizeof(T) * 1.125 * cube(n), grid_for(cube(n / 2), 1),
           dim3(kBlock), k_restrict_global<T, T>, (const T*)H.f[l], n, H.f[l - 1]);
     }
+    fin_done = false;
+    want_out = P->K > 0 ? out : nullptr;
+    want_acc = acc;
     // FMG stages on the coarse global levels in one launch
     coarse(P->Lc, 0, nullptr);
     for (int l = P->Lc + 1; l < L; ++l) {
@@ -794,7 +823,8 @@ struct Exec {
         vcycle_sr(l, l, true, r);
       }
     }
-    if (P->K > 0) {
+    want_out = nullptr;
+    if (P->K > 0 && !fin_done) {
       const Geo& G = H.geo[L - 1];
       lvl = L - 1;
       run("k_gather", (sizeof(T) + 8.0 + (acc ? 8.0 : 0.0)) * cube(P->N),

@@ -60,6 +60,10 @@ struct SmoothArgs {
   int zc;             // planes per z chunk
   int nxcd;           // blocks are dealt to this many L2 domains in turn
   int inplace;        // 1: one workgroup per segment, u updated in place
+  // output epilogue (in place only): the genuine cells go to out (n^3, the
+  // caller's FP64 solution) -- written (1) or added (2) -- instead of u
+  double* out;
+  int outmode;
 };
 
 template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE>
@@ -97,6 +101,9 @@ k_smooth_z(SmoothArgs<T> a) {
     glo[d] = B.a[d] - 1 < 0 ? 0 : B.a[d] - 1;
     ghi[d] = B.b[d] + 1 > n ? n : B.b[d] + 1;
   }
+  // genuine region of the segment (output epilogue)
+  const int S = gu.S;
+  const int gx0 = (q % S) * gu.g, gy0 = ((q / S) % S) * gu.g, gz0 = (q / (S * S)) * gu.g;
   const int tx0 = inpl ? B.a[0] : wlo[0], ty0 = inpl ? B.a[1] : wlo[1];
   const int tz0 = inpl ? B.a[2] : wlo[2], tz1 = inpl ? B.b[2] : whi[2];
   const int ox = tx0 + ti * sx, oy = ty0 + tj * sy, oz = tz0 + tk * a.zc;
@@ -144,7 +151,9 @@ k_smooth_z(SmoothArgs<T> a) {
                            : (st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H);
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
-    ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4);
+    const bool gen = col && x >= gx0 && x < gx0 + gu.g && y >= gy0 && y < gy0 + gu.g;
+    ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
+            (gen ? 128u : 0u);
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
 #pragma unroll
     for (int j = 0; j < NS + 2; ++j) U[j][r] = 0;
@@ -221,7 +230,7 @@ k_smooth_z(SmoothArgs<T> a) {
             const int c = ci[r];
             T sum = lds[b][c - 1] + lds[b][c + 1] + lds[b][c - txw] + lds[b][c + txw] +
                     U[s - 1][r] + U[s + 1][r];
-            const int nb = (int)(ok[r] >> 4) + nbz;
+            const int nb = (int)((ok[r] >> 4) & 7u) + nbz;
             if (nb == 0)
               U[s][r] = (sum - a.h2 * F[s][r]) * (T)(1.0 / 6.0);
             else
@@ -231,7 +240,17 @@ k_smooth_z(SmoothArgs<T> a) {
       }
       // plane p - NS is final
       const int zo = p - NS;
-      if (zo >= zs0 && zo < zs1) {
+      if (a.outmode) {  // genuine cells to the caller's solution
+        if (zo >= gz0 && zo < gz0 + gu.g) {
+#pragma unroll
+          for (int r = 0; r < RY; ++r) {
+            if (ok[r] & 128u) {
+              const long long io = ((long long)zo * n + ys[r]) * n + xr[r];
+              a.out[io] = a.outmode == 2 ? a.out[io] + (double)U[NS][r] : (double)U[NS][r];
+            }
+          }
+        }
+      } else if (zo >= zs0 && zo < zs1) {
         const long long pw = (long long)(zo - B.o[2]) * mm;
 #pragma unroll
         for (int r = 0; r < RY; ++r)
