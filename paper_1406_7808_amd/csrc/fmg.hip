@@ -310,7 +310,7 @@ static bool geo_ok(const Geo& g) { return g.n >= 1 && g.m >= 1 && g.S >= 1 && g.
 template <class X>
 static bool nonnull(const SmoothArgs<X>& a) {
   return a.uin && a.u && a.rhs && (a.uin != a.u || a.inplace) && geo_ok(a.gu) && geo_ok(a.gr) &&
-         geo_ok(a.gc) &&
+         geo_ok(a.gc) && (a.rmode < 0 || (a.uc && a.rc && geo_ok(a.gcr) && a.rmode <= 1)) &&
          a.txw > 2 && a.tyw > 2 && a.ntx >= 1 && a.nty >= 1 && a.ntz >= 1 && a.zc >= 1 &&
          a.nxcd >= 1;
 }
@@ -418,11 +418,13 @@ struct Exec {
 
   // one temporally blocked launch of NS half-sweeps with prologue PRO; RY
   // columns per thread; inpl: one workgroup per segment, updated in place
-  template <int NS, int RY, int PRO>
+  template <int NS, int RY, int PRO, int RES = 0>
   void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl,
-                double* out = nullptr, int outmode = 0) {
+                double* out = nullptr, int outmode = 0, int rmode = -1) {
     constexpr int NT = 1024, NC = NT * RY;
-    constexpr int WPE = (NS <= 2 && (RY == 1 || sizeof(T) == 4)) ? 8 : 4;
+    // two workgroups per CU (at most 64 VGPRs) where the kernel fits them
+    constexpr int WPE =
+        (NS <= 2 && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD && !RES))) ? 8 : 4;
     const Geo& G = H.geo[l];
     if (PRO != PRO_LOAD && (!c || !ct)) throw hip_error("internal: null coarse increment");
     SmoothArgs<T> a{};
@@ -439,6 +441,12 @@ struct Exec {
     if (outmode && (!inpl || !out)) throw hip_error("internal: output epilogue needs an in-place pass");
     a.out = out;
     a.outmode = outmode;
+    if (RES != (rmode >= 0) || (RES && (!inpl || l < 1)))
+      throw hip_error("internal: residual epilogue needs an in-place pass");
+    a.rmode = rmode;
+    a.uc = RES ? H.u[l - 1] : nullptr;
+    a.rc = RES ? H.rhs[l - 1] : nullptr;
+    a.gcr = H.geo[l > 0 ? l - 1 : 0];
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
     int ns = nseg(l);
@@ -489,9 +497,12 @@ struct Exec {
     double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
     if (outmode)  // u is not stored; the genuine cells go out in FP64 (read too when added)
-      bytes += (8.0 * outmode - sizeof(T)) * cube(P->N) - sizeof(T) * c_cells(G);
+      bytes += 8.0 * outmode * cube(P->N) - sizeof(T) * c_cells(G);
+    if (RES)  // uc and rc on the coarse target
+      bytes += 2.0 * sizeof(T) * (rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
     run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>", bytes,
-        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE>, a);
+        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE, RES>,
+        a);
   }
 
   template <int PRO>
@@ -620,7 +631,7 @@ struct Exec {
       smooth_simple(l, rhs, gr, nu);
       return false;
     }
-    bool first = true;
+    bool first = true, restricted = false;
     const bool inpl = seg_inplace(l);
     const int mx = inpl ? 4 : P->max_stages;
     while (st > 0) {
@@ -634,12 +645,19 @@ struct Exec {
         om = fin_acc ? 2 : 1;
         fin_done = true;
       }
-      if (pr == PRO_CORRECT) smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
-      else smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+      if (pr == PRO_LOAD && rmode >= 0 && inpl && ns == 2 && st == ns && !om) {
+        // the last pass of a pre-smoothing also restricts (residual epilogue)
+        smooth_z<2, 2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, true, nullptr, 0, rmode);
+        restricted = true;
+      } else if (pr == PRO_CORRECT) {
+        smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+      } else {
+        smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+      }
       st -= ns;
       first = false;
     }
-    return false;
+    return restricted;
   }
 
   // the persistent coarse-level kernel: FMG stages 0..top (mode 0) or one

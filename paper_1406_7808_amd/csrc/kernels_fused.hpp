@@ -64,14 +64,26 @@ struct SmoothArgs {
   // caller's FP64 solution) -- written (1) or added (2) -- instead of u
   double* out;
   int outmode;
+  // residual-restriction epilogue (RES kernels, in place only): uc = R u and
+  // rc = R (rhs - L u) on the coarse target -- rmode 0: C / 2 of the segment
+  // (coarse segment storage); 1: the genuine coarse cells (global level)
+  int rmode;
+  T* uc;
+  T* rc;
+  Geo gcr;
 };
 
-template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE>
+template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_smooth_z(SmoothArgs<T> a) {
   constexpr int H = NS, NC = NT * RY;
   static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT, "interpolation has its own kernel");
+  static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
   __shared__ T lds[2][NC];  // neighbour exchange, one plane per stage parity
+  // epilogue: exchange of the plane being reduced, and per-column sums over
+  // the two fine planes of a coarse plane
+  __shared__ T ldsr[RES ? NC : 1];
+  __shared__ double lsu[RES ? NC : 1], lsr[RES ? NC : 1];
 
   const Geo gu = a.gu;
   const int q = blockIdx.y;
@@ -115,7 +127,7 @@ k_smooth_z(SmoothArgs<T> a) {
 
   // steps p0..p1, padded to a multiple of PF: the padding steps only touch
   // planes past the chunk, whose results are never stored
-  const int p0 = oz - NS, p1 = zs1 - 1 + NS;
+  const int p0 = oz - NS, p1 = zs1 - 1 + NS + RES;
   const int nsteps = ((p1 - p0 + 1) + PF - 1) / PF * PF;
 
   const Box Br = seg_box(a.gr, q);
@@ -130,7 +142,11 @@ k_smooth_z(SmoothArgs<T> a) {
 
   // tile columns are numbered row-major over txw x tyw; thread t owns
   // columns t, t + NT, ...
-  T U[NS + 2][RY], F[NS + 1][RY];
+  // windows: U[j] holds plane p - j, F[j] the rhs of plane p - j (one more
+  // plane of each for the epilogue, which reduces plane p - NS - 1)
+  constexpr int NU = NS + 2 + RES, NF = NS + 1 + RES;
+  T U[NU][RY], F[NF][RY];
+  double su[RY], sr[RY];
   T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
   int xr[RY], ys[RY], uo[RY], ci[RY];
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
@@ -152,13 +168,17 @@ k_smooth_z(SmoothArgs<T> a) {
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
     const bool gen = col && x >= gx0 && x < gx0 + gu.g && y >= gy0 && y < gy0 + gu.g;
+    // epilogue: the column holding child (0,0) of a coarse target cell
+    const bool own = RES && (a.rmode == 0 ? inc && ((x - B.a[0]) & 1) == 0 && ((y - B.a[1]) & 1) == 0
+                                          : gen && (x & 1) == 0 && (y & 1) == 0);
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
-            (gen ? 128u : 0u);
+            (gen ? 128u : 0u) | (own ? 256u : 0u);
+    su[r] = sr[r] = 0.0;
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
 #pragma unroll
-    for (int j = 0; j < NS + 2; ++j) U[j][r] = 0;
+    for (int j = 0; j < NU; ++j) U[j][r] = 0;
 #pragma unroll
-    for (int j = 0; j < NS + 1; ++j) F[j][r] = 0;
+    for (int j = 0; j < NF; ++j) F[j][r] = 0;
   }
 
   // issue the loads of plane p into a ring slot (raw values, used PF steps
@@ -198,11 +218,11 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int k = 0; k < PF; ++k) {
       const int p = pb + k;
 #pragma unroll
-      for (int j = NS + 1; j > 0; --j)
+      for (int j = NU - 1; j > 0; --j)
 #pragma unroll
         for (int r = 0; r < RY; ++r) U[j][r] = U[j - 1][r];
 #pragma unroll
-      for (int j = NS; j > 0; --j)
+      for (int j = NF - 1; j > 0; --j)
 #pragma unroll
         for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
 #pragma unroll
@@ -255,6 +275,53 @@ k_smooth_z(SmoothArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < RY; ++r)
           if (ok[r] & 4u) wb[pw + uo[r]] = U[NS][r];
+      }
+      // epilogue: residual of plane zr = p - NS - 1 (its neighbours zr +- 1
+      // are final), summed over the two fine planes of each coarse plane,
+      // then over the 2 x 2 columns of each coarse cell
+      const int zr = p - NS - 1;
+      if (RES && zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
+#pragma unroll
+        for (int r = 0; r < RY; ++r) ldsr[ci[r]] = U[NS + 1][r];
+        __syncthreads();
+        const unsigned nbz = (zr == 0) + (zr == n - 1);
+        const double s2 = (double)n * (double)n;
+        const bool odd = zr & 1;  // C starts on an even plane
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          if (ok[r] & 2u) {
+            const int c = ci[r];
+            const double sn = (((double)ldsr[c - 1] + (double)ldsr[c + 1]) +
+                               ((double)ldsr[c - txw] + (double)ldsr[c + txw])) +
+                              ((double)U[NS + 2][r] + (double)U[NS][r]);
+            const double uv = (double)U[NS + 1][r];
+            const double nb = (double)(6u + ((ok[r] >> 4) & 7u) + nbz);
+            const double res = (double)F[NS + 1][r] - (sn - nb * uv) * s2;
+            su[r] = odd ? su[r] + uv : uv;
+            sr[r] = odd ? sr[r] + res : res;
+          }
+        }
+        if (odd) {
+#pragma unroll
+          for (int r = 0; r < RY; ++r) {
+            lsu[ci[r]] = su[r];
+            lsr[ci[r]] = sr[r];
+          }
+          __syncthreads();
+          const bool zt = a.rmode == 0 || (zr >= gz0 && zr < gz0 + gu.g);
+          const Box Bo = seg_box(a.gcr, q);
+#pragma unroll
+          for (int r = 0; r < RY; ++r) {
+            if (zt && (ok[r] & 256u)) {
+              const int c = ci[r];
+              const double tu = (lsu[c] + lsu[c + 1]) + (lsu[c + txw] + lsu[c + txw + 1]);
+              const double tr = (lsr[c] + lsr[c + 1]) + (lsr[c + txw] + lsr[c + txw + 1]);
+              const long long id = at(a.gcr, Bo, xr[r] >> 1, ys[r] >> 1, zr >> 1);
+              a.uc[id] = (T)(tu / 8.0);
+              a.rc[id] = (T)(tr / 8.0);
+            }
+          }
+        }
       }
     }
   }

@@ -117,10 +117,11 @@ def test_schedule_model_byte_counts():
                                  precision="fp32_refined")
     N3 = 256 ** 3
     # segmental refinement recomputes buffer cells (1.4x to 12x the genuine
-    # cells on the SR levels; its finest level takes two sweeps per pass), the
-    # refined solve runs three FP32 solves plus FP64 residuals
+    # cells on the SR levels) but its workgroup-resident segments fuse more
+    # steps per pass; the refined solve runs three FP32 solves plus FP64
+    # residuals
     assert 60 < g / N3 < 300
-    assert 1.1 < s / g < 3.5
+    assert 0.8 < s / g < 3.5
     assert r > s
 
 
