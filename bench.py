@@ -50,12 +50,16 @@ def symbol_pattern(label, dtype="double"):
     """Regular expression for the demangled symbol (as rocprofv3 prints it)
     of the kernel instantiation a profile label stands for."""
     base, _, arg = label.partition("<")
-    arg = arg.rstrip(">")
+    args = arg.rstrip(">").split(",")
     pro = {"load": 0, "interp": 1, "correct": 2}
     if base == "k_smooth_z":
-        return r"fmg::k_smooth_z<%s, \d+, %d," % (dtype, pro[arg])
+        ns = int(args[1][2:])
+        ry = int(args[2][2:])
+        res = 1 if "res" in args[3:] else 0
+        return r"fmg::k_smooth_z<%s, %d, %d, 1024, %d, \d+, \d+, %d>" % (dtype, ns, pro[args[0]],
+                                                                          ry, res)
     if base == "k_smooth_box":
-        return r"fmg::k_smooth_box<%s, %d>" % (dtype, pro[arg])
+        return r"fmg::k_smooth_box<%s, %d>" % (dtype, pro[args[0]])
     return r"fmg::%s[<(]" % base
 
 
@@ -68,7 +72,7 @@ def measured_traffic(kernel):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != source_hash() or t.get("kernel") != kernel:
+    if t.get("source_hash") != source_hash() or t.get("symbol_pattern") != symbol_pattern(kernel):
         return None
     return t.get("bytes_per_launch")
 
@@ -168,7 +172,7 @@ def main():
                     help="run the workload for rocprofv3 --pmc (solves + calibration copy)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two counter-pass CSVs")
-    ap.add_argument("--kernel", default="k_smooth_z<load>",
+    ap.add_argument("--kernel", default="k_smooth_z<load,ns4,ry2>",
                     help="profile label whose traffic --traffic-from extracts")
     ap.add_argument("--commands", default="", help="commands recorded in traffic.json")
     args = ap.parse_args()
@@ -251,15 +255,19 @@ def main():
         plan.execute(fd, u)
     stats = plan.profile_read()
     plan.profile(False)
-    # the dominant kernel: largest total time over all its levels
-    by_kernel = {}
+    # the dominant kernel: the instantiation (one rocprofv3 symbol) with the
+    # largest total time over all its levels and labels
+    by_kernel, label_of = {}, {}
     for k, v in stats.items():
         name = k.split("@")[0]
-        a = by_kernel.setdefault(name, [0, 0.0, 0.0])
+        sym = symbol_pattern(name)
+        label_of.setdefault(sym, name)
+        a = by_kernel.setdefault(sym, [0, 0.0, 0.0])
         for i in range(3):
             a[i] += v[i]
-    kern = max(by_kernel, key=lambda k: by_kernel[k][1])
-    launches, tot_ms, tot_bytes = by_kernel[kern]
+    sym = max(by_kernel, key=lambda k: by_kernel[k][1])
+    kern = label_of[sym]
+    launches, tot_ms, tot_bytes = by_kernel[sym]
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
     traffic = measured_traffic(kern)
     kernels = {k: {"launches": v[0] // 3, "ms_per_solve": round(v[1] / 3, 4),

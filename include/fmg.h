@@ -101,6 +101,28 @@ int32_t fmg_plan_create(int32_t N, const fmg_params *p, int32_t device, fmg_plan
  * serves one stream at a time and is not thread-safe. */
 int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *stream);
 
+/* Level checkpoints (the per-level state of the differentiable solve, and a
+ * validation hook): while set, every fmg_plan_execute also writes the
+ * solution of each level l right after its FMG stage (Fig. 2: after the
+ * stage's V-cycle; Fig. 5 for segment levels, whose genuine cells are
+ * written) into out[l], a DEVICE array of n_l^3 doubles with
+ * n_l = N >> (levels - 1 - l) in the layout above.  out is a HOST array of
+ * `levels` such pointers (NULL entries are skipped), copied at the call; the
+ * arrays must stay valid while set.  out == NULL clears them.  FP64 plans
+ * only (FMG_ENOTSUP otherwise). */
+int32_t fmg_plan_checkpoints(fmg_plan *plan, double *const *out);
+
+/* The comparison solver of Sec. 7 (Fig. 10): V(nu_pre, nu_post) cycles
+ * (Fig. 1) on the plan's hierarchy, starting from the guess in u, until
+ * max_c |f - L_h u|_c <= rtol * max_c |f_c| or maxit cycles; u (device, N^3)
+ * is updated in place.  *iters and *relres (host, may be NULL) receive the
+ * cycle count and the final max|f - L u| / max|f|.  Global FP64 plans only
+ * (sr_levels == 0): FMG_ENOTSUP otherwise.  Synchronizes `stream` once per
+ * cycle (the stopping test) and allocates a small temporary device buffer.
+ * FMG_EINVAL for null or overlapping f/u, rtol < 0 or maxit < 0. */
+int32_t fmg_plan_vcycles(fmg_plan *plan, const double *f, double *u, double rtol, int32_t maxit,
+                         int32_t *iters, double *relres, void *stream);
+
 /* Free the workspace (synchronizes the plan's device).  NULL is accepted. */
 int32_t fmg_plan_destroy(fmg_plan *plan);
 

@@ -220,6 +220,7 @@ struct fmg_plan {
   int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
   bool seg_inplace = true;    // segment levels: in place, one workgroup per segment
   std::set<const void*> lds_attr;  // kernels already allowed the whole LDS
+  std::vector<double*> ck;         // level checkpoints (empty: none)
   long long target_blocks = 1024;  // workgroups a fused launch aims for
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
@@ -337,6 +338,16 @@ static bool nonnull(const CoarseArgs<X>& a) {
   return true;
 }
 
+// profile label of one k_smooth_z instantiation, e.g. "k_smooth_z<load,ns2,ry1>"
+template <int NS, int PRO, int RY, int RES>
+static const char* zlabel() {
+  static const std::string s = std::string("k_smooth_z<") +
+                               (PRO == PRO_CORRECT ? "correct" : "load") + ",ns" +
+                               std::to_string(NS) + ",ry" + std::to_string(RY) +
+                               (RES ? ",res" : "") + ">";
+  return s.c_str();
+}
+
 template <class T>
 struct Exec {
   using A = T;  // smoothing arithmetic: FP64 or FP32
@@ -347,6 +358,26 @@ struct Exec {
   int lvl = -1;      // level of the launches being issued (profile label)
   // the solve's final pass may write the genuine cells to fin_out (added when
   // fin_acc) itself; fin_done records that it did
+  // level checkpoints are taken by FP64 solves when the caller set them
+  bool checkpoints() const { return sizeof(T) == 8 && !P->ck.empty(); }
+
+  // level l's solution after its FMG stage into its checkpoint (global
+  // levels: a copy; segment levels: the genuine cells)
+  void checkpoint(int l) {
+    if (!checkpoints() || !P->ck[l]) return;
+    const Geo& G = H.geo[l];
+    lvl = l;
+    if (!G.ghost) {
+      if (!dry)
+        hipcheck(hipMemcpyAsync(P->ck[l], H.u[l], sizeof(T) * (size_t)cube(G.n),
+                                hipMemcpyDeviceToDevice, s),
+                 "hipMemcpyAsync");
+      return;
+    }
+    run("k_gather", (sizeof(T) + 8.0) * cube(G.n), grid_for(cube(G.g), nseg(l)), dim3(kBlock),
+        k_gather<T>, P->ck[l], (const T*)H.u[l], G, 0);
+  }
+
   double* want_out = nullptr;  // where this solve's genuine cells go (K > 0)
   int want_acc = 0;
   double* fin_out = nullptr;
@@ -500,7 +531,7 @@ struct Exec {
       bytes += 8.0 * outmode * cube(P->N) - sizeof(T) * c_cells(G);
     if (RES)  // uc and rc on the coarse target
       bytes += 2.0 * sizeof(T) * (rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
-    run(PRO == PRO_CORRECT ? "k_smooth_z<correct>" : "k_smooth_z<load>", bytes,
+    run(zlabel<NS, PRO, RY, RES>(), bytes,
         dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE, RES>,
         a);
   }
@@ -683,6 +714,8 @@ struct Exec {
     a.nu1 = P->nu1;
     a.nu2 = P->nu2;
     a.alpha = P->alpha;
+    if (mode == 0 && checkpoints())
+      for (int l = 0; l <= top; ++l) a.ck[l] = P->ck[l];
     size_t shm = sizeof(T) * (size_t)coarse_lds_elems(a.n, top, mode);
     if ((long long)shm + 1024 > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
     // the kernel also holds a small static LDS block (level offsets)
@@ -840,6 +873,7 @@ struct Exec {
         bool r = smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP, 0, rmode);
         vcycle_sr(l, l, true, r);
       }
+      if (l < L - 1) checkpoint(l);
     }
     want_out = nullptr;
     if (P->K > 0 && !fin_done) {
@@ -867,6 +901,10 @@ static void execute(fmg_plan* P, const double* f, double* u, hipStream_t s) {
     }
     if (!P->h64.ua[L - 1]) throw hip_error("internal: finest level has no storage");
     E.fmg(f, u, 0);
+    if (!P->ck.empty() && P->ck[L - 1] && !P->virt)
+      hipcheck(hipMemcpyAsync(P->ck[L - 1], u, sizeof(double) * (size_t)cnt,
+                              hipMemcpyDeviceToDevice, s),
+               "hipMemcpyAsync");
     return;
   }
   // mixed precision: u = FMG32(f); then refine times u += FMG32(f - L u)
@@ -1051,6 +1089,41 @@ int32_t fmg_plan_execute(fmg_plan* P, const double* f, double* u, void* stream) 
   return FMG_OK;
 }
 
+static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, int maxit,
+                        double* relres, hipStream_t s);
+
+int32_t fmg_plan_checkpoints(fmg_plan* P, double* const* out) {
+  if (!P) return fail(FMG_EINVAL, "plan is NULL");
+  if (P->precision != FMG_FP64) return fail(FMG_ENOTSUP, "checkpoints need an FP64 plan");
+  if (!out) {
+    P->ck.clear();
+    return FMG_OK;
+  }
+  P->ck.assign(out, out + P->L);
+  return FMG_OK;
+}
+
+int32_t fmg_plan_vcycles(fmg_plan* P, const double* f, double* u, double rtol, int32_t maxit,
+                         int32_t* iters, double* relres, void* stream) {
+  if (!P) return fail(FMG_EINVAL, "plan is NULL");
+  if (!f || !u) return fail(FMG_EINVAL, "f or u is NULL");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(FMG_EINVAL, "rtol must be >= 0 and maxit >= 0");
+  if (P->K != 0 || P->precision != FMG_FP64)
+    return fail(FMG_ENOTSUP, "V-cycle iteration needs a global FP64 plan (sr_levels 0)");
+  size_t bytes = sizeof(double) * (size_t)cube(P->N);
+  const char* fa = (const char*)f;
+  const char* ua = (const char*)u;
+  if (fa < ua + bytes && ua < fa + bytes) return fail(FMG_EINVAL, "f and u overlap");
+  try {
+    hipcheck(hipSetDevice(P->device), "hipSetDevice");
+    int it = vcycle_solve(P, f, u, rtol, maxit, relres, (hipStream_t)stream);
+    if (iters) *iters = it;
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  return FMG_OK;
+}
+
 int32_t fmg_plan_destroy(fmg_plan* P) {
   if (!P) return FMG_OK;
   (void)hipSetDevice(P->device);
@@ -1123,29 +1196,37 @@ int32_t fmg_plan_profile_read(fmg_plan* P, fmg_kernel_stat* out, int32_t cap, in
   return FMG_OK;
 }
 
-// a10: norms of f - L u (mode 0) or u - v (mode 1); partial results in a
-// temporary device buffer, the two norms copied to the host
+// a10: norms of f - L u (mode 0), u - v (mode 1) or f (mode 2) into
+// res[0..1] (device), with nb partial pairs in part (device)
+static long long norm_blocks(int n) {
+  long long nb = (cube(n) + kNormThreads - 1) / kNormThreads;
+  return nb > 1024 ? 1024 : nb;
+}
+
+static hipError_t norms_launch(const double* a, const double* b, int n, int mode, double* part,
+                               double* res, hipStream_t st) {
+  const long long nb = norm_blocks(n);
+  hipLaunchKernelGGL(k_norms, dim3((unsigned)nb), dim3(kNormThreads), 0, st, a, b, n, mode, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kNormThreads), 0, st, (const double*)part,
+                     (int)nb, n, res);
+  return hipGetLastError();
+}
+
+// the same, results copied to the host (synchronizes st)
 static int32_t norms(const double* a, const double* b, int32_t n, int mode, double* out,
                      void* stream) {
   if (!a || !b || !out || n < 1) return fail(FMG_EINVAL, "bad arguments");
   if (a == b && mode == 0) return fail(FMG_EINVAL, "f and u must not be the same array");
   hipStream_t st = (hipStream_t)stream;
-  const long long cnt = cube(n);
-  long long nb = (cnt + kNormThreads - 1) / kNormThreads;
-  if (nb > 1024) nb = 1024;
+  const long long nb = norm_blocks(n);
   double* part = nullptr;
   if (hipMalloc(&part, sizeof(double) * (size_t)(2 * nb + 2)) != hipSuccess)
     return fail(FMG_ENOMEM, "hipMalloc failed");
   int32_t ret = FMG_OK;
   double res[2] = {0.0, 0.0};
-  hipLaunchKernelGGL(k_norms, dim3((unsigned)nb), dim3(kNormThreads), 0, st, a, b, (int)n, mode,
-                     part);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kNormThreads), 0, st, (const double*)part,
-                       (int)nb, (int)n, part + 2 * nb);
-    e = hipGetLastError();
-  }
+  hipError_t e = norms_launch(a, b, n, mode, part, part + 2 * nb, st);
   if (e == hipSuccess) e = hipMemcpyAsync(res, part + 2 * nb, sizeof res, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) ret = fail(FMG_EHIP, hipGetErrorString(e));
@@ -1155,6 +1236,49 @@ static int32_t norms(const double* a, const double* b, int32_t n, int mode, doub
     out[1] = res[1];
   }
   return ret;
+}
+
+// f4: V(nu1, nu2) cycles on the global hierarchy from the guess in u until
+// max|f - L u| <= rtol max|f| or maxit cycles (the stopping rule of the
+// oracle's iterated V-cycles); returns the cycle count
+static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, int maxit,
+                        double* relres, hipStream_t s) {
+  const int N = P->N, L = P->L;
+  Hier<double>& H = P->h64;
+  Exec<double> E{P, H, s};
+  H.ua[L - 1] = u;
+  H.ub[L - 1] = P->ws_finest;
+  for (int l = 0; l < L; ++l) H.u[l] = H.ua[l];
+  H.f[L - 1] = const_cast<double*>(f);
+  const long long nb = norm_blocks(N);
+  double* part = nullptr;
+  hipcheck(hipMalloc(&part, sizeof(double) * (size_t)(2 * nb + 4)), "hipMalloc");
+  struct Free {
+    double* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{part};
+  double* res = part + 2 * nb;
+  double h[4];
+  hipcheck(norms_launch(f, f, N, 2, part, res + 2, s), "norms");
+  int it = 0;
+  double rn = 0.0, fn = 0.0;
+  for (;;) {
+    hipcheck(norms_launch(f, H.u[L - 1], N, 0, part, res, s), "norms");
+    hipcheck(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    rn = h[0];
+    fn = h[2];
+    if (rn <= rtol * fn || it >= maxit) break;
+    E.vcycle_global(L - 1, f);
+    ++it;
+  }
+  if (H.u[L - 1] != u)
+    hipcheck(hipMemcpyAsync(u, H.u[L - 1], sizeof(double) * (size_t)cube(N),
+                            hipMemcpyDeviceToDevice, s),
+             "hipMemcpyAsync");
+  hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (relres) *relres = fn > 0 ? rn / fn : rn;
+  return it;
 }
 
 int32_t fmg_residual_norms(const double* f, const double* u, int32_t N, double* out,

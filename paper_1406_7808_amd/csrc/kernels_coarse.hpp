@@ -40,6 +40,7 @@ struct CoarseArgs {
   int mode;
   const T* rt;  // mode 1: rhs of level top
   int nu1, nu2, alpha;
+  double* ck[kCoarseMaxLevels];  // mode 0: level l's solution after its stage (or null)
 };
 
 // elements of a level's padded u
@@ -298,6 +299,16 @@ __device__ void blk_copy(T* lds, T* glob, int n) {
   }
 }
 
+// a level's solution (padded LDS) to an FP64 checkpoint array (n^3)
+template <class T>
+__device__ void blk_checkpoint(const T* lds, double* out, int n) {
+  const int n2 = n * n, cnt = n * n2;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
+    out[i] = (double)lds[pidx(n, x, y, z)];
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   extern __shared__ unsigned char smem_raw[];
@@ -343,10 +354,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
     blk_vcycle(sm, o, g, g.top, o.rt);
   } else {
     blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.n[0], g.Ainv, g.mm);
+    if (g.ck[0]) blk_checkpoint(sm + o.u[0], g.ck[0], g.n[0]);
     for (int l = 1; l <= g.top; ++l) {
       blk_interp(sm + o.u[l], g.n[l], sm + o.u[l - 1]);
       blk_gs(sm + o.u[l], sm + o.f[l], g.n[l], g.alpha);
       blk_vcycle(sm, o, g, l, o.f[l]);
+      if (g.ck[l]) blk_checkpoint(sm + o.u[l], g.ck[l], g.n[l]);
     }
   }
   blk_copy<T, false, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);

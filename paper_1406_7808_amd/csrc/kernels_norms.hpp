@@ -4,10 +4,10 @@
 // The paper reports the infinity norm of the error and of the residual
 // f - L_h u (Sec. 7, Figs. 8 and 10).  k_norms forms, per cell of an n^3 grid,
 // r = f - L_h u (mode 0, the 7-point operator with the zero Dirichlet ghosts
-// of Eq. 2) or r = f - u (mode 1), and reduces max |r| and sum r^2: each
-// thread over a grid-stride range, then across the 64 lanes of a wavefront
-// with cross-lane exchanges, then across the wavefronts of the workgroup in
-// LDS.  Each workgroup writes one partial pair; k_norms_final reduces the
+// of Eq. 2), r = f - u (mode 1) or r = f (mode 2), and reduces max |r| and
+// sum r^2: each thread over a grid-stride range, then across the 64 lanes of
+// a wavefront with cross-lane exchanges, then across the wavefronts of the
+// workgroup in LDS.  Each workgroup writes one partial pair; k_norms_final reduces the
 // partials in one workgroup in a fixed order, so results are deterministic
 // for a given grid and launch shape.
 #pragma once
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kNormThreads) k_norms(const double* __restrict
       const int x = (int)(c % n), y = (int)((c / n) % n), z = (int)(c / ((long long)n * n));
       r = f[c] - apply_L<double, double>(u, G, B, x, y, z);
     } else {
-      r = f[c] - u[c];
+      r = mode == 1 ? f[c] - u[c] : f[c];
     }
     const double a = r < 0 ? -r : r;
     mx = a > mx ? a : mx;

@@ -47,7 +47,9 @@ class _KernelStat(ctypes.Structure):
 
 
 _lib = None
-SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_destroy",
+SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_vcycles",
+           "fmg_plan_checkpoints",
+           "fmg_plan_destroy",
            "fmg_solve", "fmg_plan_workspace_bytes", "fmg_plan_profile", "fmg_plan_profile_read", "fmg_schedule_model",
            "fmg_last_error", "fmg_residual_norms", "fmg_diff_norms", "fmg_op_apply",
            "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
@@ -68,6 +70,11 @@ def lib():
     L.fmg_plan_create.restype = i32
     L.fmg_plan_execute.argtypes = [vp, vp, vp, vp]
     L.fmg_plan_execute.restype = i32
+    L.fmg_plan_vcycles.argtypes = [vp, vp, vp, ctypes.c_double, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double), vp]
+    L.fmg_plan_vcycles.restype = i32
+    L.fmg_plan_checkpoints.argtypes = [vp, ctypes.POINTER(vp)]
+    L.fmg_plan_checkpoints.restype = i32
     L.fmg_plan_destroy.argtypes = [vp]
     L.fmg_plan_destroy.restype = i32
     L.fmg_solve.argtypes = [vp, i32, pp, vp, vp]
@@ -148,6 +155,8 @@ class Plan:
     def __init__(self, N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1),
                  precision="fp64", refine_iters=2, device=None):
         self.N = N
+        self.levels = levels
+        self._ck = None
         self._p, self._keep = make_params(levels, sr_levels, segments, buffers, sweeps, precision,
                                           refine_iters)
         dev = torch.cuda.current_device() if device is None else device
@@ -166,6 +175,34 @@ class Plan:
             u = torch.empty_like(f)
         _check(lib().fmg_plan_execute(self._h, _dev(f, self.N), _dev(u, self.N), _stream(stream)))
         return u
+
+    def level_edges(self):
+        return [self.N >> (self.levels - 1 - l) for l in range(self.levels)]
+
+    def set_checkpoints(self, bufs):
+        """Per-level checkpoint arrays (a list of `levels` float64 CUDA
+        tensors of shape (n_l,)*3, or None entries); None clears them."""
+        if bufs is None:
+            self._ck = None
+            _check(lib().fmg_plan_checkpoints(self._h, None))
+            return
+        edges = self.level_edges()
+        arr = (ctypes.c_void_p * self.levels)()
+        for l, b in enumerate(bufs):
+            arr[l] = None if b is None else _dev(b, edges[l]).value
+        self._ck = list(bufs)  # keep them alive while set
+        _check(lib().fmg_plan_checkpoints(self._h, arr))
+
+    def vcycles(self, f, u, rtol=1e-4, maxit=50, stream=None):
+        """V(nu1, nu2) cycles from the guess in u (updated in place) until
+        max|f - L u| <= rtol max|f| or maxit cycles; returns (cycles, relres).
+        Global FP64 plans only.  Synchronizes the stream once per cycle."""
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        _check(lib().fmg_plan_vcycles(self._h, _dev(f, self.N), _dev(u, self.N), float(rtol),
+                                      int(maxit), ctypes.byref(it), ctypes.byref(rr),
+                                      _stream(stream)))
+        return it.value, rr.value
 
     def profile(self, enable=True):
         """Start (or stop) per-launch event timing; clears pending records."""

@@ -174,6 +174,38 @@ def test_full_size_sr(fourier256):
     plan.close()
 
 
+# --- V-cycle iteration (the comparison solver) ---------------------------------------
+
+@pytest.mark.parametrize("N,L", [(32, 5), (64, 6), (48, 5)])
+def test_vcycles_fixed_count(N, L):
+    _say("vcycles", N, L)
+    f = W.random_field(N, 900 + N)
+    u0 = W.random_field(N, 901 + N)
+    plan = fmg.Plan(N, L)
+    u = _gpu(u0)
+    it, rr = plan.vcycles(_gpu(f), u, rtol=0.0, maxit=4)
+    ref, rit, rrr = oracle.vcycles(f, L, rtol=0.0, maxit=4, u0=u0)
+    assert it == rit == 4
+    assert _rel(u, ref) <= TOL
+    assert abs(rr - rrr) <= 1e-6 * rrr
+    plan.close()
+
+
+def test_vcycles_to_tolerance():
+    N, L = 64, 6
+    f, uc, (k, a) = W.fourier(N)
+    plan = fmg.Plan(N, L)
+    u = torch.zeros((N, N, N), dtype=torch.float64, device="cuda")
+    it, rr = plan.vcycles(_gpu(f), u, rtol=1e-4, maxit=50)
+    ref, rit, rrr = oracle.vcycles(f, L, rtol=1e-4, maxit=50)
+    assert it == rit and rr <= 1e-4
+    assert _rel(u, ref) <= TOL
+    with pytest.raises(fmg.FMGError) as e:
+        fmg.Plan(N, L, sr_levels=2, segments=2, buffers=[2, 2]).vcycles(_gpu(f), u)
+    assert e.value.status == fmg.FMG_ENOTSUP
+    plan.close()
+
+
 # --- mixed precision --------------------------------------------------------------
 
 def _fp32_gap(edisc, ref):
