@@ -101,6 +101,33 @@ int32_t fmg_plan_create(int32_t N, const fmg_params *p, int32_t device, fmg_plan
  * serves one stream at a time and is not thread-safe. */
 int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *stream);
 
+/*
+ * Performance knobs of a plan.  Every valid setting computes the same solve
+ * (results agree to rounding: the smoothers differ only in forming
+ * 1/(6 + b_c) products and the order of a few sums); the batched interface
+ * and the autotuner pick them per problem size.
+ *   max_stages     half-sweeps per pass of the streaming smoother on levels
+ *                  smoothed over two copies: 2 or 4 (default 2);
+ *   seg_inplace    1: segment levels whose compute region plus an 8-cell halo
+ *                  fits 2048 columns are smoothed in place, one workgroup per
+ *                  segment, 4 half-sweeps per pass (default 1);
+ *   box            1: segment levels whose whole storage box fits the LDS of
+ *                  one workgroup use the box-resident smoother (default 1);
+ *   target_blocks  workgroups a streaming pass aims for, 64..65536
+ *                  (default 1024).
+ * fmg_plan_set_tuning re-plans the schedule on the host (no device call);
+ * FMG_EINVAL for out-of-range values.
+ */
+typedef struct {
+  int32_t max_stages;
+  int32_t seg_inplace;
+  int32_t box;
+  int32_t target_blocks;
+} fmg_tuning;
+
+int32_t fmg_plan_get_tuning(const fmg_plan *plan, fmg_tuning *out);
+int32_t fmg_plan_set_tuning(fmg_plan *plan, const fmg_tuning *tuning);
+
 /* Level checkpoints (the per-level state of the differentiable solve, and a
  * validation hook): while set, every fmg_plan_execute also writes the
  * solution of each level l right after its FMG stage (Fig. 2: after the
@@ -184,6 +211,38 @@ int32_t fmg_schedule_model(int32_t N, const fmg_params *p, fmg_schedule_stat *ou
 int32_t fmg_residual_norms(const double *f, const double *u, int32_t N, double *out,
                            void *stream);
 int32_t fmg_diff_norms(const double *u, const double *v, int32_t N, double *out, void *stream);
+
+/*
+ * Batches of independent solves (sizes, parameters and tunings may differ).
+ * The problems are spread over `streams` internal streams (1..16; longest
+ * first, each to the least loaded stream) so that small solves run side by
+ * side; problems sharing a stream and equal (N, params, tuning) share one
+ * plan's workspace.
+ *   fmg_batch_create: count problems; N, params (and tuning, or NULL for the
+ *     defaults) are HOST arrays of `count` entries, copied at the call.
+ *   fmg_batch_execute: u[i] <- FMG(f[i]) for every problem; f and u are HOST
+ *     arrays of `count` device pointers (N[i]^3 doubles each, layout above;
+ *     no u[i] may overlap another problem's f or u).  The call forks `stream`
+ *     to the internal streams and joins them back, so later work on `stream`
+ *     sees every solution.
+ *   fmg_batch_capture: records the same work for these pointers into a HIP
+ *     graph owned by the batch (replacing an earlier one); `stream` must not
+ *     be the legacy default stream.  fmg_batch_replay launches that graph:
+ *     the whole batch in one graph launch.
+ * FMG_EINVAL on a parameter error (with the problem's index in the message).
+ */
+typedef struct fmg_batch fmg_batch;
+
+int32_t fmg_batch_create(int32_t count, const int32_t *N, const fmg_params *params,
+                         const fmg_tuning *tuning, int32_t streams, int32_t device,
+                         fmg_batch **out);
+int32_t fmg_batch_execute(fmg_batch *batch, const double *const *f, double *const *u,
+                          void *stream);
+int32_t fmg_batch_capture(fmg_batch *batch, const double *const *f, double *const *u,
+                          void *stream);
+int32_t fmg_batch_replay(fmg_batch *batch, void *stream);
+int64_t fmg_batch_workspace_bytes(const fmg_batch *batch);
+int32_t fmg_batch_destroy(fmg_batch *batch);
 
 /* Message of the last non-OK status returned on this thread ("" if none). */
 const char *fmg_last_error(void);

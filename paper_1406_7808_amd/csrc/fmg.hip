@@ -13,6 +13,7 @@
 // waits inside a solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -219,6 +220,7 @@ struct fmg_plan {
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
   int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
   bool seg_inplace = true;    // segment levels: in place, one workgroup per segment
+  bool use_box = true;        // segment levels whose box fits LDS: box-resident smoother
   std::set<const void*> lds_attr;  // kernels already allowed the whole LDS
   std::vector<double*> ck;         // level checkpoints (empty: none)
   long long target_blocks = 1024;  // workgroups a fused launch aims for
@@ -558,7 +560,7 @@ struct Exec {
   // does a segment's whole storage box fit the box-resident smoother?
   bool box_fits(int l) const {
     const Geo& G = H.geo[l];
-    if (!G.ghost) return false;
+    if (!G.ghost || !P->use_box) return false;
     long long ce = cext(l);
     long long pairs = (ce + 1) / 2 * ce * ce;
     return cube(G.m) * (long long)sizeof(T) <= P->lds_max && pairs <= kBoxSlots * kBoxThreads;
@@ -930,13 +932,39 @@ static void release(fmg_plan* P) {
 
 // Fill a plan: geometry, workspace (device memory, or virtual addresses for
 // the schedule model) and the FP64 coarsest-level inverse.
+// A dry walk of the schedule (after the geometry or the tuning changed):
+// which copy of the finest global level holds the result last, so that the
+// caller's u can be that copy?  (A one-level hierarchy is never smoothed.)
+static void settle_schedule(fmg_plan* P) {
+  if (P->precision != FMG_FP64 || P->K != 0) return;
+  const int L = P->L;
+  double* fake_u = (double*)(uintptr_t)(1ull << 41);
+  double* keep_a = P->h64.ua[L - 1];
+  double* keep_b = P->h64.ub[L - 1];
+  const long long ml = P->model_launches;
+  const double mb = P->model_bytes;
+  const bool keep_virt = P->virt;
+  P->virt = true;
+  P->h64.ua[L - 1] = fake_u;  // stands for the caller's array
+  P->h64.ub[L - 1] = P->ws_finest;
+  {
+    Exec<double> E{P, P->h64, nullptr};
+    E.dry = true;
+    E.fmg((const double*)(uintptr_t)(1ull << 40), fake_u, 0);
+  }
+  P->finest_odd = P->h64.u[L - 1] != fake_u;
+  P->h64.ua[L - 1] = keep_a;
+  P->h64.ub[L - 1] = keep_b;
+  P->virt = keep_virt;
+  P->model_launches = ml;
+  P->model_bytes = mb;
+}
+
 static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt, fmg_plan** out) {
   fmg_plan* P = new (std::nothrow) fmg_plan();
   if (!P) return fail(FMG_ENOMEM, "host allocation failed");
   P->virt = virt;
   P->lds_max = 160 * 1024;
-  if (const char* e = std::getenv("FMG_MAX_STAGES")) P->max_stages = std::atoi(e) <= 2 ? 2 : 4;
-  if (const char* e = std::getenv("FMG_SEG_INPLACE")) P->seg_inplace = std::atoi(e) != 0;
   if (!virt) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)
@@ -981,20 +1009,8 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
     P->Ainv = (double*)dalloc(P, sizeof(double) * inv.size());
     if (P->precision == FMG_FP64) {
       build_hier(P, P->h64, true);
-      if (P->K == 0) {
-        // dry walk of the schedule: which copy holds the finest level last?
-        // (a one-level hierarchy is never smoothed and has no second copy)
-        P->ws_finest = P->h64.ub[P->L - 1];
-        double* fake_u = (double*)(uintptr_t)(1ull << 41);
-        P->h64.ua[P->L - 1] = fake_u;  // stands for the caller's array
-        Exec<double> E{P, P->h64, nullptr};
-        E.dry = true;
-        E.fmg((const double*)(uintptr_t)(1ull << 40), fake_u, 0);
-        P->finest_odd = P->h64.u[P->L - 1] != fake_u;
-        P->h64.ua[P->L - 1] = nullptr;
-        P->model_launches = 0;
-        P->model_bytes = 0;
-      }
+      if (P->K == 0) P->ws_finest = P->h64.ub[P->L - 1];
+      settle_schedule(P);
     } else {
       build_hier(P, P->h32, false);
       P->r32 = (float*)dalloc(P, sizeof(float) * cube(N));
@@ -1020,6 +1036,77 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
 
 // ---------------------------------------------------------------------------
 // C interface
+
+// ---------------------------------------------------------------------------
+// Batches: many independent solves (sizes may differ) spread over internal
+// streams -- longest problems first, each to the least loaded stream -- so
+// that small solves, each far from filling the GPU, run side by side.  The
+// caller's stream forks to the internal streams and joins back, so the whole
+// batch can be captured into one HIP graph and replayed with one launch.
+// Problems on one stream run one after another and share a plan when their
+// parameters and tuning agree.
+struct fmg_batch {
+  int device = 0;
+  int count = 0;
+  std::vector<int> N, plan_of, stream_of;
+  std::vector<fmg_plan*> plans;
+  std::vector<hipStream_t> streams;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long long bytes = 0;
+};
+
+static void batch_release(fmg_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto st : b->streams) (void)hipStreamDestroy(st);
+  for (auto P : b->plans) release(P);
+  delete b;
+}
+
+static bool same_params(const fmg_params& a, const fmg_params& b) {
+  if (a.levels != b.levels || a.sr_levels != b.sr_levels ||
+      a.segments_per_dim != b.segments_per_dim || a.nu_pre != b.nu_pre ||
+      a.nu_post != b.nu_post || a.alpha != b.alpha || a.precision != b.precision ||
+      a.refine_iters != b.refine_iters)
+    return false;
+  for (int i = 0; i < a.sr_levels; ++i)
+    if (a.buffer_schedule[i] != b.buffer_schedule[i]) return false;
+  return true;
+}
+
+static bool same_tuning(const fmg_tuning* a, const fmg_tuning* b) {
+  if (!a || !b) return a == b;
+  return a->max_stages == b->max_stages && a->seg_inplace == b->seg_inplace && a->box == b->box &&
+         a->target_blocks == b->target_blocks;
+}
+
+// fork the caller's stream to the internal streams, enqueue every solve, join
+static void batch_enqueue(fmg_batch* b, const double* const* f, double* const* u, hipStream_t s) {
+  hipcheck(hipEventRecord(b->fork, s), "hipEventRecord");
+  for (auto st : b->streams) hipcheck(hipStreamWaitEvent(st, b->fork, 0), "hipStreamWaitEvent");
+  for (int i = 0; i < b->count; ++i) execute(b->plans[b->plan_of[i]], f[i], u[i], b->streams[b->stream_of[i]]);
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    hipcheck(hipEventRecord(b->join[k], b->streams[k]), "hipEventRecord");
+    hipcheck(hipStreamWaitEvent(s, b->join[k], 0), "hipStreamWaitEvent");
+  }
+}
+
+static std::string batch_check_io(const fmg_batch* b, const double* const* f, double* const* u) {
+  if (!f || !u) return "f or u is NULL";
+  for (int i = 0; i < b->count; ++i) {
+    if (!f[i] || !u[i]) return "a problem's f or u is NULL";
+    size_t bytes = sizeof(double) * (size_t)cube(b->N[i]);
+    const char* fa = (const char*)f[i];
+    const char* ua = (const char*)u[i];
+    if (fa < ua + bytes && ua < fa + bytes) return "a problem's f and u overlap";
+  }
+  return "";
+}
 
 extern "C" {
 
@@ -1091,6 +1178,34 @@ int32_t fmg_plan_execute(fmg_plan* P, const double* f, double* u, void* stream) 
 
 static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, int maxit,
                         double* relres, hipStream_t s);
+
+int32_t fmg_plan_get_tuning(const fmg_plan* P, fmg_tuning* out) {
+  if (!P || !out) return fail(FMG_EINVAL, "plan or out is NULL");
+  out->max_stages = P->max_stages;
+  out->seg_inplace = P->seg_inplace ? 1 : 0;
+  out->box = P->use_box ? 1 : 0;
+  out->target_blocks = (int32_t)P->target_blocks;
+  return FMG_OK;
+}
+
+int32_t fmg_plan_set_tuning(fmg_plan* P, const fmg_tuning* t) {
+  if (!P || !t) return fail(FMG_EINVAL, "plan or tuning is NULL");
+  if (t->max_stages != 2 && t->max_stages != 4) return fail(FMG_EINVAL, "max_stages must be 2 or 4");
+  if ((t->seg_inplace != 0 && t->seg_inplace != 1) || (t->box != 0 && t->box != 1))
+    return fail(FMG_EINVAL, "seg_inplace and box must be 0 or 1");
+  if (t->target_blocks < 64 || t->target_blocks > 65536)
+    return fail(FMG_EINVAL, "target_blocks must be in 64..65536");
+  P->max_stages = t->max_stages;
+  P->seg_inplace = t->seg_inplace != 0;
+  P->use_box = t->box != 0;
+  P->target_blocks = t->target_blocks;
+  try {
+    settle_schedule(P);
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  return FMG_OK;
+}
 
 int32_t fmg_plan_checkpoints(fmg_plan* P, double* const* out) {
   if (!P) return fail(FMG_EINVAL, "plan is NULL");
@@ -1310,7 +1425,6 @@ int32_t fmg_op_smooth(double* u, const double* rhs, int32_t n, int32_t nu, void*
   int32_t ret = FMG_OK;
   {
     fmg_plan P;
-    if (const char* e = std::getenv("FMG_MAX_STAGES")) P.max_stages = std::atoi(e) <= 2 ? 2 : 4;
     P.N = n;
     P.L = 1;
     P.T = 0;
@@ -1349,6 +1463,156 @@ int32_t fmg_op_interp(const double* coarse, int32_t n, double* fine, void* strea
                      (hipStream_t)stream, fine, Gf, coarse, Gc, zc, ce);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FMG_OK : fail(FMG_EHIP, hipGetErrorString(e));
+}
+
+int32_t fmg_batch_create(int32_t count, const int32_t* N, const fmg_params* params,
+                         const fmg_tuning* tuning, int32_t nstreams, int32_t device,
+                         fmg_batch** out) {
+  if (!out) return fail(FMG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !N || !params) return fail(FMG_EINVAL, "count, N or params invalid");
+  if (nstreams < 1 || nstreams > 16) return fail(FMG_EINVAL, "streams must be in 1..16");
+  for (int i = 0; i < count; ++i) {
+    std::string e = check(N[i], &params[i]);
+    if (!e.empty()) return fail(FMG_EINVAL, "problem " + std::to_string(i) + ": " + e);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return fail(FMG_EINVAL, "invalid device");
+  }
+  if (hipSetDevice(device) != hipSuccess) return fail(FMG_EHIP, "hipSetDevice failed");
+  fmg_batch* b = new (std::nothrow) fmg_batch();
+  if (!b) return fail(FMG_ENOMEM, "host allocation failed");
+  b->device = device;
+  b->count = count;
+  b->N.assign(N, N + count);
+  b->plan_of.assign(count, -1);
+  b->stream_of.assign(count, 0);
+  const int ns = nstreams < count ? nstreams : count;
+  // longest problems first, each to the least loaded stream
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) {
+    return cube(N[a]) != cube(N[c]) ? cube(N[a]) > cube(N[c]) : a < c;
+  });
+  std::vector<double> load(ns, 0.0);
+  for (int i : order) {
+    int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->stream_of[i] = k;
+    load[k] += (double)cube(N[i]) * (params[i].precision == FMG_FP64 ? 1.0 : 2.0);
+  }
+  try {
+    for (int k = 0; k < ns; ++k) {
+      hipStream_t st;
+      hipcheck(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+      b->streams.push_back(st);
+      hipEvent_t e;
+      hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+      b->join.push_back(e);
+    }
+    hipcheck(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+    // one plan per (stream, N, parameters, tuning)
+    std::vector<int> owner;  // problem that defined each plan
+    for (int i = 0; i < count; ++i) {
+      const fmg_tuning* ti = tuning ? &tuning[i] : nullptr;
+      for (size_t j = 0; j < owner.size(); ++j) {
+        const int o = owner[j];
+        if (b->stream_of[o] == b->stream_of[i] && N[o] == N[i] && same_params(params[o], params[i]) &&
+            same_tuning(tuning ? &tuning[o] : nullptr, ti)) {
+          b->plan_of[i] = (int)j;
+          break;
+        }
+      }
+      if (b->plan_of[i] >= 0) continue;
+      fmg_plan* P = nullptr;
+      int32_t st = build_plan(N[i], &params[i], device, false, &P);
+      if (st != FMG_OK) {
+        std::string msg = "problem " + std::to_string(i) + ": " + g_err;
+        batch_release(b);
+        return fail(st, msg);
+      }
+      b->plans.push_back(P);
+      b->bytes += P->bytes;
+      if (ti) {
+        st = fmg_plan_set_tuning(P, ti);
+        if (st != FMG_OK) {
+          std::string msg = "problem " + std::to_string(i) + ": " + g_err;
+          batch_release(b);
+          return fail(st, msg);
+        }
+      }
+      b->plan_of[i] = (int)b->plans.size() - 1;
+      owner.push_back(i);
+    }
+  } catch (const hip_error& ex) {
+    batch_release(b);
+    return fail(FMG_EHIP, ex.what());
+  }
+  *out = b;
+  return FMG_OK;
+}
+
+int32_t fmg_batch_execute(fmg_batch* b, const double* const* f, double* const* u, void* stream) {
+  if (!b) return fail(FMG_EINVAL, "batch is NULL");
+  std::string e = batch_check_io(b, f, u);
+  if (!e.empty()) return fail(FMG_EINVAL, e);
+  try {
+    hipcheck(hipSetDevice(b->device), "hipSetDevice");
+    batch_enqueue(b, f, u, (hipStream_t)stream);
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  return FMG_OK;
+}
+
+int32_t fmg_batch_capture(fmg_batch* b, const double* const* f, double* const* u, void* stream) {
+  if (!b) return fail(FMG_EINVAL, "batch is NULL");
+  if (!stream) return fail(FMG_EINVAL, "capture needs a non-default stream");
+  std::string e = batch_check_io(b, f, u);
+  if (!e.empty()) return fail(FMG_EINVAL, e);
+  hipStream_t s = (hipStream_t)stream;
+  for (auto P : b->plans)
+    if (P->prof.on) return fail(FMG_EINVAL, "disable plan profiling before capture");
+  try {
+    hipcheck(hipSetDevice(b->device), "hipSetDevice");
+    if (b->exec) hipcheck(hipGraphExecDestroy(b->exec), "hipGraphExecDestroy");
+    if (b->graph) hipcheck(hipGraphDestroy(b->graph), "hipGraphDestroy");
+    b->exec = nullptr;
+    b->graph = nullptr;
+    hipcheck(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      batch_enqueue(b, f, u, s);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hipcheck(hipStreamEndCapture(s, &b->graph), "hipStreamEndCapture");
+    hipcheck(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  } catch (const hip_error& ex) {
+    return fail(FMG_EHIP, ex.what());
+  }
+  return FMG_OK;
+}
+
+int32_t fmg_batch_replay(fmg_batch* b, void* stream) {
+  if (!b) return fail(FMG_EINVAL, "batch is NULL");
+  if (!b->exec) return fail(FMG_EINVAL, "nothing captured");
+  hipError_t e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  return e == hipSuccess ? FMG_OK : fail(FMG_EHIP, hipGetErrorString(e));
+}
+
+int64_t fmg_batch_workspace_bytes(const fmg_batch* b) { return b ? b->bytes : 0; }
+
+int32_t fmg_batch_destroy(fmg_batch* b) {
+  if (!b) return FMG_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  batch_release(b);
+  return FMG_OK;
 }
 
 }  // extern "C"

@@ -46,13 +46,23 @@ class _KernelStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    """fmg_tuning: performance knobs of a plan (see include/fmg.h)."""
+    _fields_ = [("max_stages", ctypes.c_int32), ("seg_inplace", ctypes.c_int32),
+                ("box", ctypes.c_int32), ("target_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_vcycles",
-           "fmg_plan_checkpoints",
-           "fmg_plan_destroy",
-           "fmg_solve", "fmg_plan_workspace_bytes", "fmg_plan_profile", "fmg_plan_profile_read", "fmg_schedule_model",
-           "fmg_last_error", "fmg_residual_norms", "fmg_diff_norms", "fmg_op_apply",
-           "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
+           "fmg_plan_checkpoints", "fmg_plan_get_tuning", "fmg_plan_set_tuning",
+           "fmg_plan_destroy", "fmg_solve", "fmg_plan_workspace_bytes", "fmg_plan_profile",
+           "fmg_plan_profile_read", "fmg_schedule_model", "fmg_batch_create", "fmg_batch_execute",
+           "fmg_batch_capture", "fmg_batch_replay", "fmg_batch_workspace_bytes",
+           "fmg_batch_destroy", "fmg_last_error", "fmg_residual_norms", "fmg_diff_norms",
+           "fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
 
 
 def lib():
@@ -75,6 +85,23 @@ def lib():
     L.fmg_plan_vcycles.restype = i32
     L.fmg_plan_checkpoints.argtypes = [vp, ctypes.POINTER(vp)]
     L.fmg_plan_checkpoints.restype = i32
+    L.fmg_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.fmg_plan_get_tuning.restype = i32
+    L.fmg_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.fmg_plan_set_tuning.restype = i32
+    L.fmg_batch_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(_Params),
+                                   ctypes.POINTER(Tuning), i32, i32, ctypes.POINTER(vp)]
+    L.fmg_batch_create.restype = i32
+    L.fmg_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.fmg_batch_execute.restype = i32
+    L.fmg_batch_capture.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.fmg_batch_capture.restype = i32
+    L.fmg_batch_replay.argtypes = [vp, vp]
+    L.fmg_batch_replay.restype = i32
+    L.fmg_batch_workspace_bytes.argtypes = [vp]
+    L.fmg_batch_workspace_bytes.restype = ctypes.c_int64
+    L.fmg_batch_destroy.argtypes = [vp]
+    L.fmg_batch_destroy.restype = i32
     L.fmg_plan_destroy.argtypes = [vp]
     L.fmg_plan_destroy.restype = i32
     L.fmg_solve.argtypes = [vp, i32, pp, vp, vp]
@@ -193,6 +220,17 @@ class Plan:
         self._ck = list(bufs)  # keep them alive while set
         _check(lib().fmg_plan_checkpoints(self._h, arr))
 
+    @property
+    def tuning(self):
+        t = Tuning()
+        _check(lib().fmg_plan_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change performance knobs (max_stages, seg_inplace, box, target_blocks)."""
+        t = Tuning(**{**self.tuning, **kw})
+        _check(lib().fmg_plan_set_tuning(self._h, ctypes.byref(t)))
+
     def vcycles(self, f, u, rtol=1e-4, maxit=50, stream=None):
         """V(nu1, nu2) cycles from the guess in u (updated in place) until
         max|f - L u| <= rtol max|f| or maxit cycles; returns (cycles, relres).
@@ -227,6 +265,77 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Independent solves of possibly different sizes, run side by side on
+    internal streams; capture() records them into one HIP graph, replay()
+    launches it.  problems: dicts of Plan's keyword arguments plus "N";
+    tunings: None or one dict (or None) per problem."""
+
+    def __init__(self, problems, streams=4, tunings=None, device=None):
+        self.count = len(problems)
+        self.N = [int(p["N"]) for p in problems]
+        params = (_Params * self.count)()
+        self._keep = []
+        for i, p in enumerate(problems):
+            kw = {k: v for k, v in p.items() if k != "N"}
+            levels = kw.pop("levels")
+            buffers = kw.pop("buffers", ())
+            segments = kw.pop("segments", 1)
+            pp, keep = make_params(levels, buffers=buffers, segments=segments, **kw)
+            params[i] = pp
+            self._keep.append(keep)
+        tun = None
+        if tunings is not None:
+            tun = (Tuning * self.count)()
+            for i, t in enumerate(tunings):
+                tun[i] = Tuning(**{**DEFAULT_TUNING, **(t or {})})
+        Ns = (ctypes.c_int32 * self.count)(*self.N)
+        dev = torch.cuda.current_device() if device is None else device
+        h = ctypes.c_void_p()
+        _check(lib().fmg_batch_create(self.count, Ns, params, tun, streams, dev, ctypes.byref(h)))
+        self._h = h
+        self._io = None
+
+    @property
+    def workspace_bytes(self):
+        return lib().fmg_batch_workspace_bytes(self._h)
+
+    def _ptrs(self, fs, us):
+        if len(fs) != self.count or len(us) != self.count:
+            raise FMGError(FMG_EINVAL, "expected %d right-hand sides and solutions" % self.count)
+        F = (ctypes.c_void_p * self.count)(*[_dev(f, n).value for f, n in zip(fs, self.N)])
+        U = (ctypes.c_void_p * self.count)(*[_dev(u, n).value for u, n in zip(us, self.N)])
+        return F, U
+
+    def execute(self, fs, us, stream=None):
+        F, U = self._ptrs(fs, us)
+        _check(lib().fmg_batch_execute(self._h, F, U, _stream(stream)))
+        return us
+
+    def capture(self, fs, us, stream):
+        """Record the batch for these tensors (kept alive) into one graph."""
+        F, U = self._ptrs(fs, us)
+        _check(lib().fmg_batch_capture(self._h, F, U, _stream(stream)))
+        self._io = (list(fs), list(us))
+
+    def replay(self, stream=None):
+        _check(lib().fmg_batch_replay(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+DEFAULT_TUNING = {"max_stages": 2, "seg_inplace": 1, "box": 1, "target_blocks": 1024}
 
 
 def solve(f, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",
