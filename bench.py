@@ -160,6 +160,39 @@ def traffic_from(fetch_csv, write_csv, kernel, out_path, commands):
     return 0
 
 
+def batch_leg(precision, args):
+    """96 right-hand sides of edges 64, 96 and 128 (seeded), SR on the two
+    finest levels, solved side by side on 8 streams and replayed as one
+    graph; knobs tuned on the batch graph (cached per library build)."""
+    import torch
+    from paper_1406_7808_amd import batched
+    from paper_1406_7808_amd import workloads as W
+    items = W.batch()
+    edges = [N for N, _, _ in items]
+    fs = [torch.from_numpy(W.fourier_field(N, k, a)).cuda() for N, k, a in items]
+    us = [torch.empty_like(f) for f in fs]
+    b, probs = batched.build(edges, precision=precision, streams=8, tuned=True, fs=fs, us=us)
+    side = torch.cuda.Stream()
+    b.capture(fs, us, side)
+    for _ in range(max(1, args.warmup)):
+        b.replay(side)
+    side.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(side)
+    for _ in range(args.steps):
+        b.replay(side)
+    e1.record(side)
+    side.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    dof = sum(N ** 3 for N in edges)
+    out = {"ms": round(ms, 4), "dof_per_s": dof / (ms * 1e-3), "solves": len(edges),
+           "edges": {str(n): edges.count(n) for n in sorted(set(edges))}, "streams": 8,
+           "graph": True, "workspace_MB": round(b.workspace_bytes / 2 ** 20, 1)}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,7 +200,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--variants", default="sr,global,sr32r")
+    ap.add_argument("--variants", default="sr,global,sr32r,batch96,batch96_fp32r")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run the workload for rocprofv3 --pmc (solves + calibration copy)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -206,6 +239,8 @@ def main():
                       refine_iters=2),
     }
     names = [v for v in args.variants.split(",") if v]
+    batch_names = [v for v in names if v.startswith("batch96")]
+    names = [v for v in names if v not in batch_names]
     res, outs, plans = {}, {}, {}
     for name in names:
         plan = fmg.Plan(N, LEVELS, **specs[name])
@@ -245,6 +280,10 @@ def main():
         outs[name] = u.cpu().numpy()
         print("bench: %s %.3f ms/solve" % (name, ms), file=sys.stderr, flush=True)
         del graph
+
+    for name in batch_names:
+        res[name] = batch_leg("fp32_refined" if name.endswith("fp32r") else "fp64", args)
+        print("bench: %s %.3f ms per batch" % (name, res[name]["ms"]), file=sys.stderr, flush=True)
 
     # dominant kernel of the headline solve: event-timed launches
     head = names[0]

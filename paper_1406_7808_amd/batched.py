@@ -2,8 +2,8 @@
 
 Each size gets the deepest hierarchy whose coarsest edge is 2 or 3, and
 segmental refinement on its two finest levels with 4^3 segments and buffer
-widths (2, 2).  Problems with equal configurations share a tuning, found once
-by the autotuner (tune.py) and cached.
+widths (2, 2).  Problems with equal configurations share a tuning, found by
+the autotuner (tune.py) and cached.
 """
 from . import fmg
 from . import tune as _tune
@@ -25,11 +25,15 @@ def problem(N, precision="fp64", sr_levels=2, segments=4, buffers=(2, 2)):
             "buffers": tuple(buffers), "precision": precision}
 
 
-def build(edges, precision="fp64", streams=4, tuned=True, cache=None):
-    """A fmg.Batch for problems of the given edges (tuned per distinct edge)."""
+def build(edges, precision="fp64", streams=8, tuned=True, cache=None, fs=None, us=None):
+    """A fmg.Batch for problems of the given edges.  With tuned and the
+    batch's tensors (fs, us), the knobs are tuned on the batch graph itself;
+    with tuned alone, per solve."""
     probs = [problem(N, precision) for N in edges]
     tunings = None
-    if tuned:
+    if tuned and fs is not None:
+        tunings = _tune.tune_batch(probs, fs, us, streams=streams, cache=cache)[0]
+    elif tuned:
         best = {}
         for p in probs:
             key = p["N"]

@@ -8,6 +8,11 @@ solution agrees with the default's (every setting computes the same solve up
 to rounding), and keeps the fastest.  Results persist in a JSON cache keyed
 by the device, the library build and the configuration, so a batch of many
 right-hand sides tunes each distinct configuration once.
+
+Solves that run side by side compete for the GPU, so the fastest setting of
+a solve alone is not always the fastest inside a batch; tune_batch times the
+whole batch graph instead, one configuration at a time (coordinate descent
+over the distinct configurations, the others held at their current best).
 """
 import hashlib
 import itertools
@@ -108,3 +113,64 @@ def tune(N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), preci
     data[key] = {"tuning": best, "ms": best_ms, "candidates": timings}
     _save(path, data)
     return best, best_ms
+
+
+def _graph_ms(batch, fs, us, reps):
+    side = torch.cuda.Stream()
+    batch.capture(fs, us, side)
+    for _ in range(2):
+        batch.replay(side)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(side)
+    for _ in range(reps):
+        batch.replay(side)
+    e1.record(side)
+    side.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_batch(problems, fs, us, streams=8, reps=3, cache=None, refresh=False, candidates=None):
+    """Per-problem tunings for a batch (a list of dicts, one per problem),
+    chosen by timing the batch graph on the given right-hand sides."""
+    path = cache or default_cache_path()
+    classes = []  # distinct configurations, in order of appearance
+    for p in problems:
+        c = tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v) for k, v in p.items()))
+        if c not in classes:
+            classes.append(c)
+    cls_of = [classes.index(tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v)
+                                          for k, v in p.items()))) for p in problems]
+    comp = hashlib.sha256(json.dumps([classes, cls_of, streams], sort_keys=True,
+                                     default=str).encode()).hexdigest()[:16]
+    dev = torch.cuda.current_device()
+    key = "|".join(["batch", torch.cuda.get_device_properties(dev).gcnArchName, library_id(), comp])
+    data = _load(path)
+    if key in data and not refresh:
+        best = data[key]["tunings"]
+        return [best[i] for i in cls_of], data[key]["ms"]
+    cands = candidates or CANDIDATES
+    best = [dict(fmg.DEFAULT_TUNING) for _ in classes]
+
+    def run(tunings):
+        b = fmg.Batch(problems, streams=streams, tunings=[tunings[i] for i in cls_of])
+        try:
+            return _graph_ms(b, fs, us, reps)
+        finally:
+            b.close()
+
+    best_ms = run(best)
+    for ci in range(len(classes)):
+        for c in cands:
+            trial = [dict(t) for t in best]
+            trial[ci] = dict(c)
+            if trial[ci] == best[ci]:
+                continue
+            ms = run(trial)
+            if ms < best_ms:
+                best, best_ms = trial, ms
+    data = _load(path)
+    data[key] = {"tunings": best, "ms": best_ms, "classes": [dict(c) for c in classes],
+                 "streams": streams}
+    _save(path, data)
+    return [best[i] for i in cls_of], best_ms
