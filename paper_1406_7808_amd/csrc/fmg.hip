@@ -497,7 +497,8 @@ struct Exec {
       if (wext > G.n) wext = G.n;
       // tile shape: the fewest loaded columns covering the write region
       long long best = -1;
-      for (int tx = 2 * NS + 2; tx <= 256 && tx * (2 * NS + 2) <= NC; ++tx) {
+      // even widths: the kernel deals each row's columns to two colour classes
+      for (int tx = 2 * NS + 2; tx <= 256 && tx * (2 * NS + 2) <= NC; tx += 2) {
         int ty = NC / tx;
         if (ty > wext + 2 * NS) ty = wext + 2 * NS;
         if (ty < 2 * NS + 2) continue;
@@ -524,6 +525,7 @@ struct Exec {
       a.zc = (wext + ntz - 1) / ntz;
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
+    if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
     a.nxcd = ns > 1 ? 1 : P->nxcd;
     int nt = a.ntx * a.nty * a.ntz;
     int per = (nt + a.nxcd - 1) / a.nxcd;

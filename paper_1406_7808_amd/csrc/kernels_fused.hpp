@@ -148,15 +148,27 @@ k_smooth_z(SmoothArgs<T> a) {
   T U[NU][RY], F[NF][RY];
   double su[RY], sr[RY];
   T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
-  int xr[RY], ys[RY], uo[RY], ci[RY];
+  // Columns are dealt to thread slots sorted by colour class: slots
+  // [0, NC/2) hold the columns with (x + y) even, slots [NC/2, NC) those with
+  // (x + y) odd (txw is even, so every row has txw/2 of each).  In a
+  // half-sweep only one class has the colour being updated, so whole
+  // wavefronts (RY = 1) or whole slots (RY = 2: slot r holds class r) are
+  // active or idle together, and no lane computes a cell it then discards.
+  int xr[RY], ys[RY], uo[RY], ci[RY], kc[RY];
+  T dinv[RY];       // 1 / (6 + in-plane boundary faces)
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
                     // bits 4-6 boundary faces in x and y
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int c = threadIdx.x + NT * r;
-    const bool col = c < txw * tyw;
-    const int cy = c / txw, cx = c - cy * txw;
+    const int sl = threadIdx.x + NT * r;
+    const int k = sl >= NC / 2 ? 1 : 0, i = sl - k * (NC / 2), tw2 = txw >> 1;
+    const bool col = i < tw2 * tyw;
+    const int cy = col ? i / tw2 : 0;
+    // (x + y) parity of the tile column (cx, cy) is (ox + oy + cx + cy) & 1
+    const int cx = col ? 2 * (i - cy * tw2) + ((cy + k + ox + oy) & 1) : 0;
+    const int c = cy * txw + cx;
     const int x = ox - H + cx, y = oy - H + cy;
+    kc[r] = k;
     ci[r] = col ? c : 0;
     xr[r] = x;
     ys[r] = y;
@@ -167,6 +179,7 @@ k_smooth_z(SmoothArgs<T> a) {
                            : (st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H);
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+    dinv[r] = (T)1 / (T)(6 + nbxy);
     const bool gen = col && x >= gx0 && x < gx0 + gu.g && y >= gy0 && y < gy0 + gu.g;
     // epilogue: the column holding child (0,0) of a coarse target cell
     const bool own = RES && (a.rmode == 0 ? inc && ((x - B.a[0]) & 1) == 0 && ((y - B.a[1]) & 1) == 0
@@ -243,18 +256,17 @@ k_smooth_z(SmoothArgs<T> a) {
         __syncthreads();
         const bool zin = zp >= B.a[2] && zp < B.b[2];
         const int nbz = (zp == 0) + (zp == n - 1);
+        const int cls = (zp + col) & 1;  // the class whose cells have colour col on plane zp
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-          const bool act = zin && ((ok[r] & 10u) == 10u) && (((xr[r] + ys[r] + zp) & 1) == col);
+          const bool act = zin && kc[r] == cls && ((ok[r] & 10u) == 10u);
           if (act) {
             const int c = ci[r];
             T sum = lds[b][c - 1] + lds[b][c + 1] + lds[b][c - txw] + lds[b][c + txw] +
                     U[s - 1][r] + U[s + 1][r];
-            const int nb = (int)((ok[r] >> 4) & 7u) + nbz;
-            if (nb == 0)
-              U[s][r] = (sum - a.h2 * F[s][r]) * (T)(1.0 / 6.0);
-            else
-              U[s][r] = (sum - a.h2 * F[s][r]) / (T)(6 + nb);
+            T inv = dinv[r];
+            if (nbz) inv = (T)1 / (T)(6 + (int)((ok[r] >> 4) & 7u) + nbz);  // plane on a wall
+            U[s][r] = (sum - a.h2 * F[s][r]) * inv;
           }
         }
       }
