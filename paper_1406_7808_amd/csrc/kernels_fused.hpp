@@ -424,6 +424,37 @@ namespace fmg {
 constexpr int kBoxThreads = 1024;
 constexpr int kBoxSlots = 8;  // cell pairs per thread
 
+// A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
+// from linear index c0 in strides of `stride`: one set of divisions at the
+// start, then additions with at most one carry per dimension.
+struct Walk3 {
+  int i, j, k, di, dj, dk, ex, ey;
+  __device__ Walk3(int c0, int stride, int ex_, int ey_) : ex(max(ex_, 1)), ey(max(ey_, 1)) {
+    const int exy = ex * ey;  // an empty box walks a 1 x 1 plane and is never read
+    k = c0 / exy;
+    const int r = c0 - k * exy;
+    j = r / ex;
+    i = r - j * ex;
+    dk = stride / exy;
+    const int rs = stride - dk * exy;
+    dj = rs / ex;
+    di = rs - dj * ex;
+  }
+  __device__ void next() {
+    i += di;
+    j += dj;
+    k += dk;
+    if (i >= ex) {
+      i -= ex;
+      ++j;
+    }
+    if (j >= ey) {
+      j -= ey;
+      ++k;
+    }
+  }
+};
+
 template <class T>
 struct BoxArgs {
   T* u;
@@ -475,14 +506,16 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
 
   // load the box (u, or u + P(d)), four cells per thread in flight; the FAS
   // prologue also stores the loaded box as t
+  Walk3 wl(threadIdx.x, NT, m, m);
   for (int base = 0; base < mc; base += 4 * NT) {
     T v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = base + threadIdx.x + r * NT;
+      const int i = wl.i, j = wl.j, k = wl.k;
+      wl.next();
       v[r] = 0;
       if (c < mc) {
-        const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
         const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
         if (in_dom(n, x, y, z)) {
           v[r] = ub[c];
@@ -521,15 +554,17 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       fhi[d] = Bf.b[d] / 2;
     }
   }
+  Walk3 wp(threadIdx.x, NT, px, cy);
 #pragma unroll
   for (int t = 0; t < kBoxSlots; ++t) {
     const int s = threadIdx.x + t * NT;
+    const int xp = wp.i, yy = wp.j, zz = wp.k;
+    wp.next();
     li[t] = 0;
     gi[t] = 0;
     fl[t] = 0;
     r0[t] = r1[t] = 0;
     if (s < np) {
-      const int zz = s / (px * cy), yy = (s - zz * px * cy) / px, xp = s - zz * px * cy - yy * px;
       const int x = B.a[0] + 2 * xp, y = B.a[1] + yy, z = B.a[2] + zz;
       li[t] = ((z - B.o[2]) * m + (y - B.o[1])) * m + (x - B.o[0]);
       gi[t] = ((z - Br.o[2]) * a.gr.m + (y - Br.o[1])) * a.gr.m + (x - Br.o[0]);
@@ -625,9 +660,9 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   }
 
   // write back: the compute region, and the ghosts when the prologue changed them
-  for (int c = threadIdx.x; c < mc; c += NT) {
-    const int k = c / m2, j = (c - k * m2) / m, i = c - k * m2 - j * m;
-    const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
+  Walk3 ww(threadIdx.x, NT, m, m);
+  for (int c = threadIdx.x; c < mc; c += NT, ww.next()) {
+    const int x = B.o[0] + ww.i, y = B.o[1] + ww.j, z = B.o[2] + ww.k;
     if (!in_dom(n, x, y, z)) continue;
     const bool inC = x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1] && z >= B.a[2] &&
                      z < B.b[2];
@@ -652,8 +687,8 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   }
   const Box Bo = seg_box(a.gcr, q);
   const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ncc = ex * ey * (hi[2] - lo[2]);
-  auto child0 = [&](int cc, long long& id) -> int {  // LDS index of the (0,0,0) child
-    const int K = cc / (ex * ey), J = (cc - K * ex * ey) / ex, I = cc - K * ex * ey - J * ex;
+  auto child0 = [&](const Walk3& w, long long& id) -> int {  // LDS index of the (0,0,0) child
+    const int I = w.i, J = w.j, K = w.k;
     id = at(a.gcr, Bo, lo[0] + I, lo[1] + J, lo[2] + K);
     return ((2 * (lo[2] + K) - B.o[2]) * m + (2 * (lo[1] + J) - B.o[1])) * m +
            (2 * (lo[0] + I) - B.o[0]);
@@ -663,9 +698,10 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
             (((double)bu[l + m2] + (double)bu[l + m2 + 1]) +
              ((double)bu[l + m2 + m] + (double)bu[l + m2 + m + 1])));
   };
-  for (int cc = threadIdx.x; cc < ncc; cc += NT) {
+  Walk3 wu(threadIdx.x, NT, ex, ey);
+  for (int cc = threadIdx.x; cc < ncc; cc += NT, wu.next()) {
     long long id;
-    const int l = child0(cc, id);
+    const int l = child0(wu, id);
     a.uc[id] = (T)(sum8(l) / 8.0);
   }
   __syncthreads();
@@ -677,9 +713,10 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
     }
   }
   __syncthreads();
-  for (int cc = threadIdx.x; cc < ncc; cc += NT) {
+  Walk3 wr(threadIdx.x, NT, ex, ey);
+  for (int cc = threadIdx.x; cc < ncc; cc += NT, wr.next()) {
     long long id;
-    const int l = child0(cc, id);
+    const int l = child0(wr, id);
     a.rc[id] = (T)(sum8(l) / 8.0);
   }
 }
