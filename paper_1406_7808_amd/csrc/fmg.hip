@@ -696,8 +696,9 @@ struct Exec {
   }
 
   // the persistent coarse-level kernel: FMG stages 0..top (mode 0) or one
-  // V-cycle on level top with right-hand side rt (mode 1)
-  void coarse(int top, int mode, const T* rt) {
+  // V-cycle on level top with right-hand side rt (mode 1); fas: rt is the
+  // restricted residual and the kernel forms the FAS right-hand side and t
+  void coarse(int top, int mode, const T* rt, int fas = 0) {
     lvl = top;
     CoarseArgs<T> a;
     std::memset(&a, 0, sizeof a);
@@ -715,6 +716,8 @@ struct Exec {
     a.top = top;
     a.mode = mode;
     a.rt = rt;
+    a.fas = mode == 1 ? fas : 0;
+    if (a.fas) bytes += sizeof(T) * cube(a.n[top]);  // t written
     a.nu1 = P->nu1;
     a.nu2 = P->nu2;
     a.alpha = P->alpha;
@@ -730,11 +733,10 @@ struct Exec {
 
 
 
-  // restriction of u and of the residual onto the coarse target cells, then
-  // the coarse right-hand side and t
   // restriction of u and of the residual onto the coarse target cells
   // (skipped when the smoothing pass did it), then the coarse right-hand side
-  // and t (skipped when the coarse level's first pass forms them)
+  // and t (skipped when the coarse level's first pass, or the coarse-level
+  // kernel, forms them)
   void descend(int l, const T* rhs, Geo gr, int mode, int whole_f, bool restricted = false,
                bool rhs_deferred = false) {
     lvl = l;
@@ -808,15 +810,19 @@ struct Exec {
 
   // FAS V-cycle on global level l with right-hand side rhs (Fig. 1)
   // presmoothed: S^nu1 has already been applied (fused with the FMG step)
-  void vcycle_global(int l, const T* rhs, bool presmoothed = false) {
+  // fas: rhs holds the restricted residual only, the coarse kernel forms the
+  // FAS right-hand side (levels up to Lc)
+  void vcycle_global(int l, const T* rhs, bool presmoothed = false, bool fas = false) {
     if (l <= P->Lc) {
-      coarse(l, 1, rhs);
+      coarse(l, 1, rhs, fas ? 1 : 0);
       return;
     }
+    if (fas) throw hip_error("internal: deferred FAS right-hand side above the coarse levels");
     const Geo& G = H.geo[l];
     if (!presmoothed) smooth(l, rhs, G, P->nu1);
-    descend(l, rhs, G, 0, 1);
-    vcycle_global(l - 1, H.rhs[l - 1]);
+    const bool cf = l - 1 <= P->Lc;
+    descend(l, rhs, G, 0, 1, false, cf);
+    vcycle_global(l - 1, H.rhs[l - 1], false, cf);
     smooth(l, rhs, G, P->nu2, PRO_CORRECT);
   }
 
@@ -837,8 +843,9 @@ struct Exec {
       descend(l, rhs, gr, 0, 0, restricted, next_fas);
       vcycle_sr(l - 1, top, false, false, next_fas);
     } else {
-      descend(l, rhs, gr, 1, 1, restricted);  // owner-computes transition restriction
-      vcycle_global(l - 1, H.rhs[l - 1]);
+      const bool cf = l - 1 <= P->Lc;
+      descend(l, rhs, gr, 1, 1, restricted, cf);  // owner-computes transition restriction
+      vcycle_global(l - 1, H.rhs[l - 1], false, cf);
     }
     if (l == P->L - 1) {  // the solve's last pass: deliver the genuine cells directly
       fin_out = want_out;

@@ -9,7 +9,10 @@
 // It performs either
 //   mode 0: FMG stages 0..top (Fig. 2 of the paper): u_0 = L_0^-1 f_0, then
 //           per level Pi, S^alpha and one FAS V-cycle with rhs f_l, or
-//   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt.
+//   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt;
+//           with fas, rt holds the restricted residual of the level above and
+//           the kernel first forms the FAS right-hand side rt + L u (Eq. 4)
+//           and stores t = u, the values the coarse-grid correction subtracts.
 //
 // LDS layout: each level's u is stored with a one-cell halo of zeros
 // ((n+2)^3 elements), so a 7-point sum reads its six neighbours without
@@ -38,7 +41,8 @@ struct CoarseArgs {
   int mm;
   int top;
   int mode;
-  const T* rt;  // mode 1: rhs of level top
+  const T* rt;  // mode 1: rhs of level top (with fas: R res of the level above)
+  int fas;      // mode 1: form the FAS right-hand side rt + L u and t = u of level top
   int nu1, nu2, alpha;
   double* ck[kCoarseMaxLevels];  // mode 0: level l's solution after its stage (or null)
 };
@@ -272,6 +276,25 @@ __device__ void blk_vcycle(T* sm, const CoarseOffsets& o, const CoarseArgs<T>& g
   }
 }
 
+// FAS right-hand side of the top level in LDS: r += L u (Eq. 2, in FP64) on
+// every cell, and t = u to global memory; u padded, r plain
+template <class T>
+__device__ void blk_fas_rhs(const T* u, T* r, T* t, int n) {
+  const int n2 = n * n, cnt = n * n2, P = n + 2, P2 = P * P;
+  const double s2 = (double)n * (double)n;
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    const int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
+    const int p = pidx(n, x, y, z);
+    const double v = (double)u[p];
+    const double s = (((double)u[p - 1] + (double)u[p + 1]) + ((double)u[p - P] + (double)u[p + P])) +
+                     ((double)u[p - P2] + (double)u[p + P2]);
+    const int nb = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
+    t[c] = u[p];
+    r[c] = (T)((double)r[c] + (s - (double)(6 + nb) * v) * s2);
+  }
+  __syncthreads();
+}
+
 // copy an n^3 level between global memory (plain) and LDS (padded or plain);
 // up to four loads per thread are in flight before the stores
 template <class T, bool IN, bool PAD>
@@ -351,6 +374,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   }
   __syncthreads();
   if (g.mode == 1) {
+    if (g.fas) blk_fas_rhs(sm + o.u[g.top], sm + o.rt, g.t[g.top], g.n[g.top]);
     blk_vcycle(sm, o, g, g.top, o.rt);
   } else {
     blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.n[0], g.Ainv, g.mm);

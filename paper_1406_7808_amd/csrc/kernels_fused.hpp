@@ -423,6 +423,7 @@ namespace fmg {
 // cell in every half-sweep.
 constexpr int kBoxThreads = 1024;
 constexpr int kBoxSlots = 8;  // cell pairs per thread
+constexpr int kBoxLoads = 4;  // box cells per thread in flight while loading
 
 // A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
 // from linear index c0 in strides of `stride`: one set of divisions at the
@@ -504,13 +505,13 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   const T* __restrict__ rb = a.rhs + Br.base;
   const bool fas = PRO == PRO_LOAD && a.fas > 0;
 
-  // load the box (u, or u + P(d)), four cells per thread in flight; the FAS
-  // prologue also stores the loaded box as t
+  // load the box (u, or u + P(d)), kBoxLoads cells per thread in flight; the
+  // FAS prologue also stores the loaded box as t
   Walk3 wl(threadIdx.x, NT, m, m);
-  for (int base = 0; base < mc; base += 4 * NT) {
-    T v[4];
+  for (int base = 0; base < mc; base += kBoxLoads * NT) {
+    T v[kBoxLoads];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kBoxLoads; ++r) {
       const int c = base + threadIdx.x + r * NT;
       const int i = wl.i, j = wl.j, k = wl.k;
       wl.next();
@@ -527,7 +528,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kBoxLoads; ++r) {
       const int c = base + threadIdx.x + r * NT;
       if (c < mc) {
         bu[c] = v[r];
