@@ -32,6 +32,40 @@ struct Box {
   long long base;
 };
 
+// A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
+// from linear index c0 in strides of `stride`: one set of divisions at the
+// start, then additions with at most one carry per dimension.  A thread whose
+// c0 is at or past lim has no cell and skips the divisions.
+struct Walk3 {
+  int i, j, k, di, dj, dk, ex, ey;
+  __device__ Walk3(int c0, int stride, int ex_, int ey_, int lim = 0x7fffffff)
+      : i(0), j(0), k(0), di(0), dj(0), dk(0), ex(max(ex_, 1)), ey(max(ey_, 1)) {
+    if (c0 >= lim) return;
+    const int exy = ex * ey;  // an empty box walks a 1 x 1 plane and is never read
+    k = c0 / exy;
+    const int r = c0 - k * exy;
+    j = r / ex;
+    i = r - j * ex;
+    dk = stride / exy;
+    const int rs = stride - dk * exy;
+    dj = rs / ex;
+    di = rs - dj * ex;
+  }
+  __device__ void next() {
+    i += di;
+    j += dj;
+    k += dk;
+    if (i >= ex) {
+      i -= ex;
+      ++j;
+    }
+    if (j >= ey) {
+      j -= ey;
+      ++k;
+    }
+  }
+};
+
 __host__ __device__ inline Geo global_geo(int n) {
   Geo G;
   G.n = n; G.S = 1; G.g = n; G.J = 0; G.m = n; G.ghost = 0;

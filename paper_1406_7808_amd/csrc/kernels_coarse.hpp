@@ -85,18 +85,25 @@ template <class T>
 __device__ inline GsCell<T> gs_cell(int i, int n, int half) {
   GsCell<T> g;
   g.v = i < half;
-  const int ii = g.v ? i : 0;  // idle slots read a valid cell and store nothing
-  const int hx = n >> 1;
-  const int row = ii / hx, xh = ii - row * hx;
-  const int z = row / n, y = row - z * n;
-  const int q = (y + z) & 1;
-  const int x0 = 2 * xh + q, x1 = 2 * xh + 1 - q;
-  g.p = pidx(n, x0, y, z);
-  g.c = (z * n + y) * n + x0;
-  g.d = x1 - x0;
-  const int nyz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
-  g.inv0 = inv_diag<T>(nyz + (x0 == 0) + (x0 == n - 1));
-  g.inv1 = inv_diag<T>(nyz + (x1 == 0) + (x1 == n - 1));
+  // idle slots point at cell (0,0,0), read valid cells and store nothing;
+  // wavefronts without a cell of this level skip the index arithmetic
+  g.p = pidx(n, 0, 0, 0);
+  g.c = 0;
+  g.d = 1;
+  g.inv0 = g.inv1 = (T)0;
+  if (g.v) {
+    const int hx = n >> 1;
+    const int row = i / hx, xh = i - row * hx;
+    const int z = row / n, y = row - z * n;
+    const int q = (y + z) & 1;
+    const int x0 = 2 * xh + q, x1 = 2 * xh + 1 - q;
+    g.p = pidx(n, x0, y, z);
+    g.c = (z * n + y) * n + x0;
+    g.d = x1 - x0;
+    const int nyz = (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
+    g.inv0 = inv_diag<T>(nyz + (x0 == 0) + (x0 == n - 1));
+    g.inv1 = inv_diag<T>(nyz + (x1 == 0) + (x1 == n - 1));
+  }
   return g;
 }
 
@@ -137,11 +144,12 @@ __device__ void blk_gs(T* u, const T* rhs, int n, int nu) {
 // rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.
 template <class T>
 __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc) {
-  const int nc = n / 2, nc2 = nc * nc, cc = nc * nc2;
+  const int nc = n / 2, cc = nc * nc * nc;
   const int P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
-    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
+  Walk3 w(threadIdx.x, blockDim.x, nc, nc, cc);  // (I, J, K) of coarse cell c
+  for (int c = threadIdx.x; c < cc; c += blockDim.x, w.next()) {
+    const int K = w.k, J = w.j, I = w.i;
     double su = 0.0, sr = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) {
@@ -161,8 +169,9 @@ __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc
   __syncthreads();
   const int Pc = nc + 2, Pc2 = Pc * Pc;
   const double sc2 = (double)nc * (double)nc;
-  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
-    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
+  Walk3 w2(threadIdx.x, blockDim.x, nc, nc, cc);
+  for (int c = threadIdx.x; c < cc; c += blockDim.x, w2.next()) {
+    const int K = w2.k, J = w2.j, I = w2.i;
     const int p = pidx(nc, I, J, K);
     const double v = (double)uc[p];
     const double s = (((double)uc[p - 1] + (double)uc[p + 1]) +
@@ -179,10 +188,11 @@ __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc
 // u and w padded, t plain
 template <class T>
 __device__ void blk_correct(T* u, int n, const T* w, const T* t) {
-  const int nc = n / 2, nc2 = nc * nc, cc = nc * nc2;
+  const int nc = n / 2, cc = nc * nc * nc;
   const int P = n + 2, P2 = P * P;
-  for (int c = threadIdx.x; c < cc; c += blockDim.x) {
-    const int K = c / nc2, r = c - K * nc2, J = r / nc, I = r - J * nc;
+  Walk3 wk(threadIdx.x, blockDim.x, nc, nc, cc);
+  for (int c = threadIdx.x; c < cc; c += blockDim.x, wk.next()) {
+    const int K = wk.k, J = wk.j, I = wk.i;
     const T d = w[pidx(nc, I, J, K)] - t[c];
     const int p = pidx(n, 2 * I, 2 * J, 2 * K);
     T v[8];
@@ -199,9 +209,10 @@ __device__ void blk_correct(T* u, int n, const T* w, const T* t) {
 // padded coarse c onto the padded fine u
 template <class T>
 __device__ void blk_interp(T* u, int n, const T* c) {
-  const int n2 = n * n, cnt = n * n2, nc = n / 2;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
+  const int cnt = n * n * n, nc = n / 2;
+  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x, w.next()) {
+    const int x = w.i, y = w.j, z = w.k;
     const int f[3] = {x, y, z};
     int p[3], r[3];
     for (int d = 0; d < 3; ++d) {
@@ -280,10 +291,11 @@ __device__ void blk_vcycle(T* sm, const CoarseOffsets& o, const CoarseArgs<T>& g
 // every cell, and t = u to global memory; u padded, r plain
 template <class T>
 __device__ void blk_fas_rhs(const T* u, T* r, T* t, int n) {
-  const int n2 = n * n, cnt = n * n2, P = n + 2, P2 = P * P;
+  const int cnt = n * n * n, P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
-    const int z = c / n2, y = (c - z * n2) / n, x = c - z * n2 - y * n;
+  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x, w.next()) {
+    const int x = w.i, y = w.j, z = w.k;
     const int p = pidx(n, x, y, z);
     const double v = (double)u[p];
     const double s = (((double)u[p - 1] + (double)u[p + 1]) + ((double)u[p - P] + (double)u[p + P])) +
@@ -299,17 +311,18 @@ __device__ void blk_fas_rhs(const T* u, T* r, T* t, int n) {
 // up to four loads per thread are in flight before the stores
 template <class T, bool IN, bool PAD>
 __device__ void blk_copy(T* lds, T* glob, int n) {
-  const int n2 = n * n, cnt = n * n2, NT = blockDim.x;
+  const int cnt = n * n * n, NT = blockDim.x;
+  Walk3 w(threadIdx.x, NT, n, n, cnt);
   for (int base = 0; base < cnt; base += 4 * NT) {
     T v[4];
     int li[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int i = base + threadIdx.x + k * NT;
-      const int ii = i < cnt ? i : 0;
-      const int z = ii / n2, y = (ii - z * n2) / n, x = ii - z * n2 - y * n;
-      li[k] = PAD ? pidx(n, x, y, z) : ii;
-      v[k] = (i < cnt) ? (IN ? glob[ii] : lds[li[k]]) : (T)0;
+      const bool in = i < cnt;
+      li[k] = !in ? 0 : PAD ? pidx(n, w.i, w.j, w.k) : i;
+      w.next();
+      v[k] = in ? (IN ? glob[i] : lds[li[k]]) : (T)0;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -325,11 +338,10 @@ __device__ void blk_copy(T* lds, T* glob, int n) {
 // a level's solution (padded LDS) to an FP64 checkpoint array (n^3)
 template <class T>
 __device__ void blk_checkpoint(const T* lds, double* out, int n) {
-  const int n2 = n * n, cnt = n * n2;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const int z = i / n2, y = (i - z * n2) / n, x = i - z * n2 - y * n;
-    out[i] = (double)lds[pidx(n, x, y, z)];
-  }
+  const int cnt = n * n * n;
+  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x, w.next())
+    out[i] = (double)lds[pidx(n, w.i, w.j, w.k)];
 }
 
 template <class T>

@@ -425,37 +425,6 @@ constexpr int kBoxThreads = 1024;
 constexpr int kBoxSlots = 8;  // cell pairs per thread
 constexpr int kBoxLoads = 4;  // box cells per thread in flight while loading
 
-// A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
-// from linear index c0 in strides of `stride`: one set of divisions at the
-// start, then additions with at most one carry per dimension.
-struct Walk3 {
-  int i, j, k, di, dj, dk, ex, ey;
-  __device__ Walk3(int c0, int stride, int ex_, int ey_) : ex(max(ex_, 1)), ey(max(ey_, 1)) {
-    const int exy = ex * ey;  // an empty box walks a 1 x 1 plane and is never read
-    k = c0 / exy;
-    const int r = c0 - k * exy;
-    j = r / ex;
-    i = r - j * ex;
-    dk = stride / exy;
-    const int rs = stride - dk * exy;
-    dj = rs / ex;
-    di = rs - dj * ex;
-  }
-  __device__ void next() {
-    i += di;
-    j += dj;
-    k += dk;
-    if (i >= ex) {
-      i -= ex;
-      ++j;
-    }
-    if (j >= ey) {
-      j -= ey;
-      ++k;
-    }
-  }
-};
-
 template <class T>
 struct BoxArgs {
   T* u;
