@@ -37,6 +37,7 @@
 // u_c = (sum of in-domain neighbours - h^2 rhs_c) / (6 + b_c), with the
 // division replaced by a product with the precomputed 1 / (6 + b_c).
 #pragma once
+#include <type_traits>
 #include "grid.hpp"
 #include "kernels_simple.hpp"
 
@@ -79,10 +80,16 @@ k_smooth_z(SmoothArgs<T> a) {
   constexpr int H = NS, NC = NT * RY;
   static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT, "interpolation has its own kernel");
   static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
-  __shared__ T lds[2][NC];  // neighbour exchange, one plane per stage parity
-  // epilogue: exchange of the plane being reduced, and per-column sums over
-  // the two fine planes of a coarse plane
-  __shared__ T ldsr[RES ? NC : 1];
+  // neighbour exchange: per step parity, the idle class of the NS planes the
+  // step's stages update (rank-indexed, see below)
+  __shared__ T lds[2][NS][NC / 2];
+  // epilogue: exchange of the plane being reduced (per step parity: the
+  // previous step's is the plane below), each column's rhs of that plane, and
+  // per-column sums over the two fine planes of a coarse plane (indexed by
+  // slot: each half holds one class by rank, as in the stages)
+  __shared__ T ldsr[RES ? 2 : 1][RES ? NC : 1];
+  __shared__ T lsf[RES ? NC : 1];
+  __shared__ T invd[8];  // 1 / (6 + nb) for nb = 0..6 boundary faces
   __shared__ double lsu[RES ? NC : 1], lsr[RES ? NC : 1];
 
   const Geo gu = a.gu;
@@ -125,10 +132,11 @@ k_smooth_z(SmoothArgs<T> a) {
   const int zs0 = ghosts ? glo[2] : oz, zs1 = ghosts ? ghi[2] : oz1;  // planes stored
   const long long mm = (long long)gu.m * gu.m;
 
-  // steps p0..p1, padded to a multiple of PF: the padding steps only touch
-  // planes past the chunk, whose results are never stored
+  // steps p0..p1, padded to an even count (steps run in pairs): the padding
+  // step only touches planes past the chunk, whose results are never stored
+  static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
   const int p0 = oz - NS, p1 = zs1 - 1 + NS + RES;
-  const int nsteps = ((p1 - p0 + 1) + PF - 1) / PF * PF;
+  const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box(a.gr, q);
   const Box Bc = seg_box(a.gc, q);
@@ -142,34 +150,46 @@ k_smooth_z(SmoothArgs<T> a) {
 
   // tile columns are numbered row-major over txw x tyw; thread t owns
   // columns t, t + NT, ...
-  // windows: U[j] holds plane p - j, F[j] the rhs of plane p - j (one more
-  // plane of each for the epilogue, which reduces plane p - NS - 1)
-  constexpr int NU = NS + 2 + RES, NF = NS + 1 + RES;
+  // windows: U[j] holds plane p - j, F[j] the rhs of plane p - j (the
+  // epilogue, which reduces plane p - NS - 1, takes the plane below and the
+  // rhs from LDS)
+  constexpr int NU = NS + 2, NF = NS + 1;
   T U[NU][RY], F[NF][RY];
-  double su[RY], sr[RY];
   T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
   // Columns are dealt to thread slots sorted by colour class: slots
-  // [0, NC/2) hold the columns with (x + y) even, slots [NC/2, NC) those with
-  // (x + y) odd (txw is even, so every row has txw/2 of each).  In a
-  // half-sweep only one class has the colour being updated, so whole
-  // wavefronts (RY = 1) or whole slots (RY = 2: slot r holds class r) are
-  // active or idle together, and no lane computes a cell it then discards.
-  int xr[RY], ys[RY], uo[RY], ci[RY], kc[RY];
-  T dinv[RY];       // 1 / (6 + in-plane boundary faces)
+  // [0, NC/2) hold the columns of one (x + y) parity, slots [NC/2, NC) the
+  // other (txw is even, so every row has txw/2 of each).  In a half-sweep only
+  // one class has the colour being updated, so whole wavefronts (RY = 1) or
+  // whole slots (RY = 2) are active or idle together, and no lane computes a
+  // cell it then discards.  The half [NC/2, NC) holds parity c0 ^ 1 with
+  // c0 = (p0 - 1) & 1: every stage of step p0 + j updates parity (p - 1) & 1
+  // (see the step), which is then the class of half j & 1.
+  // A column's rank in its class is i = cy txw/2 + cx/2; the exchange holds
+  // one class per plane indexed by rank, so a wavefront's LDS accesses are
+  // unit stride (no bank conflicts).  The in-plane neighbours of a column are
+  // in the other class, at ranks i - 1 + (cx & 1), i + (cx & 1) (x) and
+  // i -+ txw/2 (y).
+  int xr[RY], ys[RY], uo[RY];
+  const int c0 = (p0 - 1) & 1;
+  // half and rank of slot r
+  auto kbh = [&](int r) -> int { return threadIdx.x + NT * r >= NC / 2 ? 1 : 0; };
+  auto rnk = [&](int r) -> int {
+    const int sl = threadIdx.x + NT * r;
+    return sl >= NC / 2 ? sl - NC / 2 : sl;
+  };
+  bool lact[RY];  // the slot's column is updated (inside C, not a tile edge)
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
-                    // bits 4-6 boundary faces in x and y
+                    // bits 4-6 boundary faces in x and y, bit7 genuine, bit8 owns a
+                    // coarse column (epilogue), bit9 cx odd
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int sl = threadIdx.x + NT * r;
-    const int k = sl >= NC / 2 ? 1 : 0, i = sl - k * (NC / 2), tw2 = txw >> 1;
+    const int h = sl >= NC / 2 ? 1 : 0, i = sl - h * (NC / 2), tw2 = txw >> 1, k = h ^ c0;
     const bool col = i < tw2 * tyw;
     const int cy = col ? i / tw2 : 0;
     // (x + y) parity of the tile column (cx, cy) is (ox + oy + cx + cy) & 1
     const int cx = col ? 2 * (i - cy * tw2) + ((cy + k + ox + oy) & 1) : 0;
-    const int c = cy * txw + cx;
     const int x = ox - H + cx, y = oy - H + cy;
-    kc[r] = k;
-    ci[r] = col ? c : 0;
     xr[r] = x;
     ys[r] = y;
     const bool st = col && x >= wlo[0] && x < whi[0] && y >= wlo[1] && y < whi[1];
@@ -179,14 +199,13 @@ k_smooth_z(SmoothArgs<T> a) {
                            : (st && cx >= H && cx < txw - H && cy >= H && cy < tyw - H);
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
-    dinv[r] = (T)1 / (T)(6 + nbxy);
     const bool gen = col && x >= gx0 && x < gx0 + gu.g && y >= gy0 && y < gy0 + gu.g;
     // epilogue: the column holding child (0,0) of a coarse target cell
     const bool own = RES && (a.rmode == 0 ? inc && ((x - B.a[0]) & 1) == 0 && ((y - B.a[1]) & 1) == 0
                                           : gen && (x & 1) == 0 && (y & 1) == 0);
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
-            (gen ? 128u : 0u) | (own ? 256u : 0u);
-    su[r] = sr[r] = 0.0;
+            (gen ? 128u : 0u) | (own ? 256u : 0u) | ((unsigned)(cx & 1) << 9);
+    lact[r] = inc && inner;
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
 #pragma unroll
     for (int j = 0; j < NU; ++j) U[j][r] = 0;
@@ -224,118 +243,147 @@ k_smooth_z(SmoothArgs<T> a) {
     }
   };
 
+  if (threadIdx.x < 7) invd[threadIdx.x] = (T)1 / (T)(6 + (int)threadIdx.x);  // read after a barrier
 #pragma unroll
   for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Qt[k], Vu[k], Vf[k]);
-  for (int pb = p0; pb < p0 + nsteps; pb += PF) {
+  // step p0 + j with J = j & 1: the stages update the slots of half J
+  auto step = [&](auto Jc, int p) {
+    constexpr int J = decltype(Jc)::value, kq = J % PF;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int p = pb + k;
+    for (int j = NU - 1; j > 0; --j)
 #pragma unroll
-      for (int j = NU - 1; j > 0; --j)
+      for (int r = 0; r < RY; ++r) U[j][r] = U[j - 1][r];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) U[j][r] = U[j - 1][r];
+    for (int j = NF - 1; j > 0; --j)
 #pragma unroll
-      for (int j = NF - 1; j > 0; --j)
+      for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
+    for (int r = 0; r < RY; ++r) {
+      const T v = PRO == PRO_CORRECT ? Qu[kq][r] + (Qd[kq][r] - Qt[kq][r]) : Qu[kq][r];
+      U[0][r] = ((Vu[kq] >> r) & 1u) ? v : (T)0;
+      F[0][r] = ((Vf[kq] >> r) & 1u) ? Qf[kq][r] : (T)0;
+    }
+    fetch(p + PF, Qu[kq], Qf[kq], Qd[kq], Qt[kq], Vu[kq], Vf[kq]);
+    // NS half-sweeps as a wavefront: stage s applies half-sweep s (colour
+    // (s - 1) & 1) to plane p - s.  Its cells read the other colour of that
+    // plane as the previous step left it (no stage of this step changes it),
+    // the plane above from stage s - 1 of this step and the plane below from
+    // the previous step (both in this thread's registers).  So one exchange
+    // per step serves all stages, and every stage updates the same parity,
+    // (p - s + (s - 1)) & 1 = (p - 1) & 1: half J.
+#pragma unroll
+    for (int s = 1; s <= NS; ++s)
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (kbh(r) != J) lds[J][s - 1][rnk(r)] = U[s][r];
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s <= NS; ++s) {
+      const int zp = p - s;
+      if (zp < B.a[2] || zp >= B.b[2]) continue;  // uniform over the block
+      const int nbz = (zp == 0) + (zp == n - 1);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const T v = PRO == PRO_CORRECT ? Qu[k][r] + (Qd[k][r] - Qt[k][r]) : Qu[k][r];
-        U[0][r] = ((Vu[k] >> r) & 1u) ? v : (T)0;
-        F[0][r] = ((Vf[k] >> r) & 1u) ? Qf[k][r] : (T)0;
+        if (kbh(r) != J) continue;  // compile-time for RY = 2, per wavefront for RY = 1
+        // every lane of the slot computes; lanes whose column is not updated
+        // keep their value
+        // the stencil reads around the slot's rank, or around rank tw2 for
+        // columns that are never updated, so that every read is in bounds
+        const T* pl = lds[J][s - 1];
+        const int tw2 = txw >> 1, i = lact[r] ? rnk(r) : tw2;
+        const int xn = i - 1 + (int)((ok[r] >> 9) & 1u);
+        // the plane above (just updated by stage s - 1) is added last
+        const T sum = (((pl[xn] + pl[xn + 1]) + (pl[i - tw2] + pl[i + tw2])) + U[s + 1][r]) +
+                      U[s - 1][r];
+        const T inv = invd[(int)((ok[r] >> 4) & 7u) + nbz];
+        const T nv = (sum - a.h2 * F[s][r]) * inv;
+        U[s][r] = lact[r] ? nv : U[s][r];
       }
-      fetch(p + PF, Qu[k], Qf[k], Qd[k], Qt[k], Vu[k], Vf[k]);
-      // NS half-sweeps as a wavefront: stage s updates plane p - s
-#pragma unroll
-      for (int s = 1; s <= NS; ++s) {
-        const int zp = p - s;
-        const int col = (s - 1) & 1;
-        const int b = s & 1;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) lds[b][ci[r]] = U[s][r];
-        __syncthreads();
-        const bool zin = zp >= B.a[2] && zp < B.b[2];
-        const int nbz = (zp == 0) + (zp == n - 1);
-        const int cls = (zp + col) & 1;  // the class whose cells have colour col on plane zp
+    }
+    // plane p - NS is final
+    const int zo = p - NS;
+    if (a.outmode) {  // genuine cells to the caller's solution
+      if (zo >= gz0 && zo < gz0 + gu.g) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-          const bool act = zin && kc[r] == cls && ((ok[r] & 10u) == 10u);
-          if (act) {
-            const int c = ci[r];
-            T sum = lds[b][c - 1] + lds[b][c + 1] + lds[b][c - txw] + lds[b][c + txw] +
-                    U[s - 1][r] + U[s + 1][r];
-            T inv = dinv[r];
-            if (nbz) inv = (T)1 / (T)(6 + (int)((ok[r] >> 4) & 7u) + nbz);  // plane on a wall
-            U[s][r] = (sum - a.h2 * F[s][r]) * inv;
+          if (ok[r] & 128u) {
+            const long long io = ((long long)zo * n + ys[r]) * n + xr[r];
+            a.out[io] = a.outmode == 2 ? a.out[io] + (double)U[NS][r] : (double)U[NS][r];
           }
         }
       }
-      // plane p - NS is final
-      const int zo = p - NS;
-      if (a.outmode) {  // genuine cells to the caller's solution
-        if (zo >= gz0 && zo < gz0 + gu.g) {
+    } else if (zo >= zs0 && zo < zs1) {
+      const long long pw = (long long)(zo - B.o[2]) * mm;
 #pragma unroll
-          for (int r = 0; r < RY; ++r) {
-            if (ok[r] & 128u) {
-              const long long io = ((long long)zo * n + ys[r]) * n + xr[r];
-              a.out[io] = a.outmode == 2 ? a.out[io] + (double)U[NS][r] : (double)U[NS][r];
-            }
-          }
+      for (int r = 0; r < RY; ++r)
+        if (ok[r] & 4u) wb[pw + uo[r]] = U[NS][r];
+    }
+    // epilogue: residual of plane zr = p - NS - 1 (its neighbours zr +- 1
+    // are final), summed over the two fine planes of each coarse plane,
+    // then over the 2 x 2 columns of each coarse cell
+    const int zr = p - NS - 1;
+    if (RES) {  // every step: plane p - NS - 1 into the exchange of parity J
+#pragma unroll
+      for (int r = 0; r < RY; ++r) ldsr[J][threadIdx.x + NT * r] = U[NS + 1][r];
+    }
+    if (RES && zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
+      // slot sl's column at [sl]; pn: the slot of the same rank in the other half
+      auto pnb = [&](int r) -> int {
+        const int sl = threadIdx.x + NT * r;
+        return sl >= NC / 2 ? sl - NC / 2 : sl + NC / 2;
+      };
+      __syncthreads();
+      const unsigned nbz = (zr == 0) + (zr == n - 1);
+      const double s2 = (double)n * (double)n;
+      const bool odd = zr & 1;  // C starts on an even plane
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (ok[r] & 2u) {  // C lies NS columns inside the tile: neighbours are in it
+          const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
+          const int xn = pn - 1 + (int)((ok[r] >> 9) & 1u);
+          const T* pl = ldsr[J];
+          const double sn = (((double)pl[xn] + (double)pl[xn + 1]) +
+                             ((double)pl[pn - tw2] + (double)pl[pn + tw2])) +
+                            ((double)ldsr[J ^ 1][sl] + (double)U[NS][r]);
+          const double uv = (double)U[NS + 1][r];
+          const double nb = (double)(6u + ((ok[r] >> 4) & 7u) + nbz);
+          const double res = (double)lsf[sl] - (sn - nb * uv) * s2;
+          // the column's sums over the two fine planes, kept in its own LDS entry
+          lsu[sl] = odd ? lsu[sl] + uv : uv;
+          lsr[sl] = odd ? lsr[sl] + res : res;
         }
-      } else if (zo >= zs0 && zo < zs1) {
-        const long long pw = (long long)(zo - B.o[2]) * mm;
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-          if (ok[r] & 4u) wb[pw + uo[r]] = U[NS][r];
       }
-      // epilogue: residual of plane zr = p - NS - 1 (its neighbours zr +- 1
-      // are final), summed over the two fine planes of each coarse plane,
-      // then over the 2 x 2 columns of each coarse cell
-      const int zr = p - NS - 1;
-      if (RES && zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
-#pragma unroll
-        for (int r = 0; r < RY; ++r) ldsr[ci[r]] = U[NS + 1][r];
+      if (odd) {
         __syncthreads();
-        const unsigned nbz = (zr == 0) + (zr == n - 1);
-        const double s2 = (double)n * (double)n;
-        const bool odd = zr & 1;  // C starts on an even plane
+        const bool zt = a.rmode == 0 || (zr >= gz0 && zr < gz0 + gu.g);
+        const Box Bo = seg_box(a.gcr, q);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-          if (ok[r] & 2u) {
-            const int c = ci[r];
-            const double sn = (((double)ldsr[c - 1] + (double)ldsr[c + 1]) +
-                               ((double)ldsr[c - txw] + (double)ldsr[c + txw])) +
-                              ((double)U[NS + 2][r] + (double)U[NS][r]);
-            const double uv = (double)U[NS + 1][r];
-            const double nb = (double)(6u + ((ok[r] >> 4) & 7u) + nbz);
-            const double res = (double)F[NS + 1][r] - (sn - nb * uv) * s2;
-            su[r] = odd ? su[r] + uv : uv;
-            sr[r] = odd ? sr[r] + res : res;
-          }
-        }
-        if (odd) {
-#pragma unroll
-          for (int r = 0; r < RY; ++r) {
-            lsu[ci[r]] = su[r];
-            lsr[ci[r]] = sr[r];
-          }
-          __syncthreads();
-          const bool zt = a.rmode == 0 || (zr >= gz0 && zr < gz0 + gu.g);
-          const Box Bo = seg_box(a.gcr, q);
-#pragma unroll
-          for (int r = 0; r < RY; ++r) {
-            if (zt && (ok[r] & 256u)) {
-              const int c = ci[r];
-              const double tu = (lsu[c] + lsu[c + 1]) + (lsu[c + txw] + lsu[c + txw + 1]);
-              const double tr = (lsr[c] + lsr[c + 1]) + (lsr[c + txw] + lsr[c + txw + 1]);
-              const long long id = at(a.gcr, Bo, xr[r] >> 1, ys[r] >> 1, zr >> 1);
-              a.uc[id] = (T)(tu / 8.0);
-              a.rc[id] = (T)(tr / 8.0);
-            }
+          if (zt && (ok[r] & 256u)) {
+            // the 2 x 2 columns (cx, cy) .. (cx + 1, cy + 1): this slot, the
+            // other half at ranks + (cx & 1) and + txw/2, and this half at
+            // rank + txw/2 + (cx & 1)
+            const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
+            const int od = (int)((ok[r] >> 9) & 1u);
+            const double tu = (lsu[sl] + lsu[pn + od]) + (lsu[pn + tw2] + lsu[sl + tw2 + od]);
+            const double tr = (lsr[sl] + lsr[pn + od]) + (lsr[pn + tw2] + lsr[sl + tw2 + od]);
+            const long long id = at(a.gcr, Bo, xr[r] >> 1, ys[r] >> 1, zr >> 1);
+            a.uc[id] = (T)(tu / 8.0);
+            a.rc[id] = (T)(tr / 8.0);
           }
         }
       }
     }
+    if (RES) {  // the rhs of plane p - NS, which the next step reduces
+#pragma unroll
+      for (int r = 0; r < RY; ++r) lsf[threadIdx.x + NT * r] = F[NS][r];
+    }
+  };
+  for (int pb = p0; pb < p0 + nsteps; pb += 2) {
+    step(std::integral_constant<int, 0>{}, pb);
+    // keep the two steps apart: interleaving them only lengthens live ranges
+    __builtin_amdgcn_sched_barrier(0);
+    step(std::integral_constant<int, 1>{}, pb + 1);
   }
 }
 
