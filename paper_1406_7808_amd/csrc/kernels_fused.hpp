@@ -471,7 +471,11 @@ namespace fmg {
 // cell in every half-sweep.
 constexpr int kBoxThreads = 1024;
 constexpr int kBoxSlots = 8;  // cell pairs per thread
-constexpr int kBoxLoads = 4;  // box cells per thread in flight while loading
+// box cells per thread in flight while loading (bounded by registers: the
+// slots' right-hand sides are in flight too), fewer with the correction
+// prologue (three loads per cell)
+constexpr int kBoxLoads = 8;
+constexpr int kBoxLoadsCorrect = 6;
 
 template <class T>
 struct BoxArgs {
@@ -522,40 +526,9 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   const T* __restrict__ rb = a.rhs + Br.base;
   const bool fas = PRO == PRO_LOAD && a.fas > 0;
 
-  // load the box (u, or u + P(d)), kBoxLoads cells per thread in flight; the
-  // FAS prologue also stores the loaded box as t
-  Walk3 wl(threadIdx.x, NT, m, m);
-  for (int base = 0; base < mc; base += kBoxLoads * NT) {
-    T v[kBoxLoads];
-#pragma unroll
-    for (int r = 0; r < kBoxLoads; ++r) {
-      const int c = base + threadIdx.x + r * NT;
-      const int i = wl.i, j = wl.j, k = wl.k;
-      wl.next();
-      v[r] = 0;
-      if (c < mc) {
-        const int x = B.o[0] + i, y = B.o[1] + j, z = B.o[2] + k;
-        if (in_dom(n, x, y, z)) {
-          v[r] = ub[c];
-          if (PRO == PRO_CORRECT) {
-            const long long ic = at(a.gc, Bc, x >> 1, y >> 1, z >> 1);
-            v[r] = v[r] + (a.d[ic] - a.dt[ic]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kBoxLoads; ++r) {
-      const int c = base + threadIdx.x + r * NT;
-      if (c < mc) {
-        bu[c] = v[r];
-        if (fas) a.t[B.base + c] = v[r];
-      }
-    }
-  }
-
   // cell pairs of C: pair (xp, y, z) holds x = a0 + 2 xp and x + 1; the
-  // right-hand side and diagonal inverse of both cells stay in registers
+  // right-hand side and diagonal inverse of both cells stay in registers.
+  // Set up first, so that the right-hand side loads overlap the box loads.
   const int cx = B.b[0] - B.a[0], cy = B.b[1] - B.a[1], cz = B.b[2] - B.a[2];
   const int px = (cx + 1) / 2, np = px * cy * cz;
   int li[kBoxSlots], gi[kBoxSlots];
@@ -599,6 +572,46 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       ns = t + 1;
     }
   }
+  // load the box (u, or u + P(d)) in batches of LB cells per thread, every
+  // load of a batch in flight together (lanes outside the domain read element
+  // 0 and store 0); the FAS prologue also stores the loaded box as t, after
+  // the batch's LDS writes (a store ahead of them would hold each write back
+  // until it completes)
+  constexpr int LB = PRO == PRO_LOAD ? kBoxLoads : kBoxLoadsCorrect;
+  Walk3 wl(threadIdx.x, NT, m, m);
+  for (int base = 0; base < mc; base += LB * NT) {
+    T vu[LB], vd[LB], vt[LB];
+    unsigned vin = 0;
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int c = base + threadIdx.x + r * NT;
+      const int x = B.o[0] + wl.i, y = B.o[1] + wl.j, z = B.o[2] + wl.k;
+      wl.next();
+      const bool in = c < mc && in_dom(n, x, y, z);
+      vin |= (in ? 1u : 0u) << r;
+      vu[r] = ub[in ? c : 0];
+      if (PRO == PRO_CORRECT) {
+        const long long ic = in ? at(a.gc, Bc, x >> 1, y >> 1, z >> 1) : 0;
+        vd[r] = a.d[ic];
+        vt[r] = a.dt[ic];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const T v = PRO == PRO_CORRECT ? vu[r] + (vd[r] - vt[r]) : vu[r];
+      vu[r] = ((vin >> r) & 1u) ? v : (T)0;
+      const int c = base + threadIdx.x + r * NT;
+      if (c < mc) bu[c] = vu[r];
+    }
+    if (fas) {
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const int c = base + threadIdx.x + r * NT;
+        if (c < mc) a.t[B.base + c] = vu[r];
+      }
+    }
+  }
+
   __syncthreads();
 
   const double s2 = (double)n * (double)n;
