@@ -344,7 +344,8 @@ static bool nonnull(const CoarseArgs<X>& a) {
 template <int NS, int PRO, int RY, int RES>
 static const char* zlabel() {
   static const std::string s = std::string("k_smooth_z<") +
-                               (PRO == PRO_CORRECT ? "correct" : "load") + ",ns" +
+                               (PRO == PRO_CORRECT ? "correct" : PRO == PRO_INTERP ? "interp" : "load") +
+                               ",ns" +
                                std::to_string(NS) + ",ry" + std::to_string(RY) +
                                (RES ? ",res" : "") + ">";
   return s.c_str();
@@ -526,10 +527,15 @@ struct Exec {
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
+    // the interpolation prologue loads the coarse columns under a tile, one per thread
+    if (PRO == PRO_INTERP && (!inpl || ((a.txw >> 1) + 3) * ((a.tyw >> 1) + 3) > NT))
+      throw hip_error("internal: tile too wide for the interpolation prologue");
     a.nxcd = ns > 1 ? 1 : P->nxcd;
     int nt = a.ntx * a.nty * a.ntz;
     int per = (nt + a.nxcd - 1) / a.nxcd;
-    double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
+    // u read: whole, plus a quarter for the correction's w and t, or only the
+    // coarse u (an eighth) for the interpolation prologue
+    double rd = PRO == PRO_CORRECT ? 1.25 : PRO == PRO_INTERP ? 0.125 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
     if (outmode)  // u is not stored; the genuine cells go out in FP64 (read too when added)
       bytes += 8.0 * outmode * cube(P->N) - sizeof(T) * c_cells(G);
@@ -546,9 +552,15 @@ struct Exec {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
-    else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
-    else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
+    if constexpr (PRO == PRO_INTERP) {  // the interpolation prologue: in-place passes only
+      if (!inpl) throw hip_error("internal: interpolation prologue off the in-place path");
+      if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
+      else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
+    } else {
+      if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
+      else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
+      else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
+    }
   }
 
   // can level l's segments be smoothed in place, one workgroup each, with
@@ -649,12 +661,17 @@ struct Exec {
     // the coarse-grid correction adds w - t of level l-1 (formed per cell)
     const T* d = l > 0 ? H.u[l - 1] : nullptr;
     const T* dt = l > 0 ? H.t[l - 1] : nullptr;
-    if (pro == PRO_INTERP) {
+    int st = 2 * nu;
+    const bool boxp = st > 0 && P->fused && box_fits(l);
+    // the first in-place z pass forms the FMG interpolation itself, unless it
+    // is also the pass that restricts
+    const bool zint = pro == PRO_INTERP && !boxp && P->fused && st > 0 && seg_inplace(l) &&
+                      !(rmode >= 0 && st <= 2);
+    if (pro == PRO_INTERP && !zint) {
       interp(l);
       pro = PRO_LOAD;
     }
-    int st = 2 * nu;
-    if (st > 0 && P->fused && box_fits(l)) {
+    if (boxp) {
       smooth_box(l, rhs, gr, nu, pro, d, dt, Gc, fas, rmode);
       return rmode >= 0 && pro != PRO_CORRECT;
     }
@@ -686,6 +703,8 @@ struct Exec {
         restricted = true;
       } else if (pr == PRO_CORRECT) {
         smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+      } else if (pr == PRO_INTERP) {
+        smooth_z_ns<PRO_INTERP>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       } else {
         smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       }

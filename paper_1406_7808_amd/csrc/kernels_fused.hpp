@@ -52,7 +52,7 @@ struct SmoothArgs {
   Geo gu;
   const T* rhs;
   Geo gr;
-  const T* c;   // coarse w (correct: the increment is w - t)
+  const T* c;   // coarse w (correct: the increment is w - t), or coarse u (interpolation)
   const T* ct;  // coarse t (correct)
   Geo gc;
   T h2;
@@ -78,7 +78,8 @@ template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_smooth_z(SmoothArgs<T> a) {
   constexpr int H = NS, NC = NT * RY;
-  static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT, "interpolation has its own kernel");
+  static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT || (PRO == PRO_INTERP && RY == 2),
+                "interpolation prologue: in-place passes");
   static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
   // neighbour exchange: per step parity, the idle class of the NS planes the
   // step's stages update (rank-indexed, see below)
@@ -90,6 +91,8 @@ k_smooth_z(SmoothArgs<T> a) {
   __shared__ T ldsr[RES ? 2 : 1][RES ? NC : 1];
   __shared__ T lsf[RES ? NC : 1];
   __shared__ T invd[8];  // 1 / (6 + nb) for nb = 0..6 boundary faces
+  // interpolation prologue: the coarse plane under the tile, per step parity
+  __shared__ T lci[PRO == PRO_INTERP ? 2 : 1][PRO == PRO_INTERP ? NT : 1];
   __shared__ double lsu[RES ? NC : 1], lsr[RES ? NC : 1];
 
   const Geo gu = a.gu;
@@ -128,7 +131,7 @@ k_smooth_z(SmoothArgs<T> a) {
   const int ox = tx0 + ti * sx, oy = ty0 + tj * sy, oz = tz0 + tk * a.zc;
   if (ox >= (inpl ? B.b[0] : whi[0]) || oy >= (inpl ? B.b[1] : whi[1]) || oz >= tz1) return;
   int oz1 = oz + a.zc < tz1 ? oz + a.zc : tz1;
-  const bool ghosts = inpl && PRO == PRO_CORRECT;
+  const bool ghosts = inpl && PRO != PRO_LOAD;  // the prologue changed the ghosts too
   const int zs0 = ghosts ? glo[2] : oz, zs1 = ghosts ? ghi[2] : oz1;  // planes stored
   const long long mm = (long long)gu.m * gu.m;
 
@@ -143,7 +146,7 @@ k_smooth_z(SmoothArgs<T> a) {
   T* __restrict__ wb = a.u + B.base;
   const T* __restrict__ ub = a.uin + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
-  const T* __restrict__ cd = PRO == PRO_CORRECT ? a.c + Bc.base : nullptr;
+  const T* __restrict__ cd = PRO != PRO_LOAD ? a.c + Bc.base : nullptr;
   const T* __restrict__ cdt = PRO == PRO_CORRECT ? a.ct + Bc.base : nullptr;
   const long long rmm = (long long)a.gr.m * a.gr.m;
   const long long cmm = (long long)a.gc.m * a.gc.m;
@@ -156,6 +159,10 @@ k_smooth_z(SmoothArgs<T> a) {
   constexpr int NU = NS + 2, NF = NS + 1;
   T U[NU][RY], F[NF][RY];
   T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
+  // interpolation prologue: this thread's coarse value of a fetched coarse
+  // plane in the ring, and the xy-interpolated coarse planes lo and lo + 1 of
+  // the current fine plane (lo = floor((p - 1) / 2))
+  T Qi[PF], clo[RY], chi[RY];
   // Columns are dealt to thread slots sorted by colour class: slots
   // [0, NC/2) hold the columns of one (x + y) parity, slots [NC/2, NC) the
   // other (txw is even, so every row has txw/2 of each).  In a half-sweep only
@@ -178,6 +185,22 @@ k_smooth_z(SmoothArgs<T> a) {
     return sl >= NC / 2 ? sl - NC / 2 : sl;
   };
   bool lact[RY];  // the slot's column is updated (inside C, not a tile edge)
+  // interpolation prologue: the tile's threads load the coarse columns under
+  // the tile, ctx x cty from (cX0, cY0), one each, into LDS.  Per slot: the
+  // LDS index of the coarse column (X0, Y0) under its column and, in ok bits
+  // 10-13, where X1 / Y1 lie: next (odd x / y) or previous, or reflected at a
+  // wall (X1 = X0, sign -1)
+  const int cX0 = ((ox - H) >> 1) - 1, cY0 = ((oy - H) >> 1) - 1;
+  const int ctx = (txw >> 1) + 3, ctn = ctx * ((tyw >> 1) + 3);
+  int tco = 0;  // this thread's coarse column (offset in the coarse box), if any
+  bool tcv = false;
+  if (PRO == PRO_INTERP && (int)threadIdx.x < ctn) {
+    const int X = cX0 + (int)threadIdx.x % ctx, Y = cY0 + (int)threadIdx.x / ctx;
+    tcv = X >= 0 && X < a.gc.n && Y >= 0 && Y < a.gc.n && X >= Bc.o[0] && X < Bc.o[0] + a.gc.m &&
+          Y >= Bc.o[1] && Y < Bc.o[1] + a.gc.m;
+    tco = tcv ? (Y - Bc.o[1]) * a.gc.m + (X - Bc.o[0]) : 0;
+  }
+  int io[PRO == PRO_INTERP ? RY : 1];
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
                     // bits 4-6 boundary faces in x and y, bit7 genuine, bit8 owns a
                     // coarse column (epilogue), bit9 cx odd
@@ -206,6 +229,15 @@ k_smooth_z(SmoothArgs<T> a) {
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
             (gen ? 128u : 0u) | (own ? 256u : 0u) | ((unsigned)(cx & 1) << 9);
     lact[r] = inc && inner;
+    if (PRO == PRO_INTERP) {
+      const int nc = a.gc.n, X0 = x >> 1, Y0 = y >> 1;
+      const int X1 = (x & 1) ? X0 + 1 : X0 - 1, Y1 = (y & 1) ? Y0 + 1 : Y0 - 1;
+      const bool rx = X1 < 0 || X1 >= nc, ry = Y1 < 0 || Y1 >= nc;
+      // stored columns lie one coarse column inside the coarse tile on each side
+      io[r] = st ? (Y0 - cY0) * ctx + (X0 - cX0) : ctx + 1;
+      ok[r] |= ((unsigned)(x & 1) << 10) | (rx ? 1u << 11 : 0u) | ((unsigned)(y & 1) << 12) |
+               (ry ? 1u << 13 : 0u);
+    }
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
 #pragma unroll
     for (int j = 0; j < NU; ++j) U[j][r] = 0;
@@ -218,8 +250,33 @@ k_smooth_z(SmoothArgs<T> a) {
   // read fetch the first element of the same array and their validity bit
   // masks the value at use -- so loads in flight can be counted exactly.
   unsigned Vu[PF], Vf[PF];
-  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], T(&qt)[RY], unsigned& vu,
+  // interpolation prologue: this thread's load of coarse plane P (reflected at
+  // the walls); threads without a coarse column, and planes outside the coarse
+  // box, read its first element
+  auto fetch_c = [&](int P) -> T {
+    if (P < 0) P = -1 - P;
+    else if (P >= a.gc.n) P = 2 * a.gc.n - 1 - P;
+    const bool v = tcv && P >= Bc.o[2] && P < Bc.o[2] + a.gc.m;
+    return cd[v ? (long long)(P - Bc.o[2]) * cmm + tco : 0];
+  };
+  // ... and the xy interpolation of slot r from the coarse plane in LDS
+  // (weights 9, 3, 3, 1 / 16; a reflected neighbour enters with sign -1);
+  // flip: the plane itself was reflected
+  auto cxy = [&](const T* pl, int r, bool flip) -> T {
+    const unsigned f = ok[r];
+    const int dx = (f & (1u << 11)) ? 0 : ((f & (1u << 10)) ? 1 : -1);
+    const int dy = (f & (1u << 13)) ? 0 : ((f & (1u << 12)) ? ctx : -ctx);
+    const int i0 = io[r];
+    const T q0 = pl[i0], q1 = pl[i0 + dx], q2 = pl[i0 + dy], q3 = pl[i0 + dx + dy];
+    const T s1 = (f & (1u << 11)) ? -q1 : q1;
+    const T s2 = (f & (1u << 13)) ? -q2 : q2;
+    const T s3 = (((f >> 11) ^ (f >> 13)) & 1u) ? -q3 : q3;
+    const T c = (T)0.5625 * q0 + ((T)0.1875 * (s1 + s2) + (T)0.0625 * s3);
+    return flip ? -c : c;
+  };
+  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], T(&qt)[RY], T& qi, unsigned& vu,
                    unsigned& vf) {
+    if (PRO == PRO_INTERP) qi = fetch_c(((p - 1) >> 1) + 1);
     const bool zs = p >= wlo[2] && p < whi[2];
     const bool zcin = p >= B.a[2] && p < B.b[2];
     const long long pu = (long long)(p - B.o[2]) * mm;
@@ -233,7 +290,7 @@ k_smooth_z(SmoothArgs<T> a) {
       const bool w = v && zcin && (ok[r] & 2u);
       vu |= (v ? 1u : 0u) << r;
       vf |= (w ? 1u : 0u) << r;
-      qu[r] = ub[v ? pu + uo[r] : 0];
+      if (PRO != PRO_INTERP) qu[r] = ub[v ? pu + uo[r] : 0];
       if (PRO == PRO_CORRECT) {
         const long long ic = v ? pc + ((ys[r] >> 1) - Bc.o[1]) * a.gc.m + ((xr[r] >> 1) - Bc.o[0]) : 0;
         qd[r] = cd[ic];
@@ -244,8 +301,15 @@ k_smooth_z(SmoothArgs<T> a) {
   };
 
   if (threadIdx.x < 7) invd[threadIdx.x] = (T)1 / (T)(6 + (int)threadIdx.x);  // read after a barrier
+  if (PRO == PRO_INTERP) {  // the window starts with lo(p0) in both planes
+    const int lo = (p0 - 1) >> 1;
+    if ((int)threadIdx.x < ctn) lci[1][threadIdx.x] = fetch_c(lo);
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Qt[k], Vu[k], Vf[k]);
+    for (int r = 0; r < RY; ++r) clo[r] = chi[r] = cxy(lci[1], r, lo < 0 || lo >= a.gc.n);
+  }
+#pragma unroll
+  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Qt[k], Qi[k], Vu[k], Vf[k]);
   // step p0 + j with J = j & 1: the stages update the slots of half J
   auto step = [&](auto Jc, int p) {
     constexpr int J = decltype(Jc)::value, kq = J % PF;
@@ -257,13 +321,17 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int j = NF - 1; j > 0; --j)
 #pragma unroll
       for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
+    const unsigned vuk = Vu[kq];  // U[0] of the interpolation prologue is formed after the exchange
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const T v = PRO == PRO_CORRECT ? Qu[kq][r] + (Qd[kq][r] - Qt[kq][r]) : Qu[kq][r];
-      U[0][r] = ((Vu[kq] >> r) & 1u) ? v : (T)0;
+      if (PRO != PRO_INTERP) {
+        const T v = PRO == PRO_CORRECT ? Qu[kq][r] + (Qd[kq][r] - Qt[kq][r]) : Qu[kq][r];
+        U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
+      }
       F[0][r] = ((Vf[kq] >> r) & 1u) ? Qf[kq][r] : (T)0;
     }
-    fetch(p + PF, Qu[kq], Qf[kq], Qd[kq], Qt[kq], Vu[kq], Vf[kq]);
+    if (PRO == PRO_INTERP && (int)threadIdx.x < ctn) lci[J][threadIdx.x] = Qi[kq];
+    fetch(p + PF, Qu[kq], Qf[kq], Qd[kq], Qt[kq], Qi[kq], Vu[kq], Vf[kq]);
     // NS half-sweeps as a wavefront: stage s applies half-sweep s (colour
     // (s - 1) & 1) to plane p - s.  Its cells read the other colour of that
     // plane as the previous step left it (no stage of this step changes it),
@@ -277,6 +345,21 @@ k_smooth_z(SmoothArgs<T> a) {
       for (int r = 0; r < RY; ++r)
         if (kbh(r) != J) lds[J][s - 1][rnk(r)] = U[s][r];
     __syncthreads();
+    if (PRO == PRO_INTERP) {
+      // plane p lies between coarse planes lo and lo + 1; lo advances on odd
+      // p, and p takes 3/4 of the nearer one (FMG interpolation: trilinear,
+      // odd reflection at the walls)
+      const int Pn = ((p - 1) >> 1) + 1;
+      const bool flip = Pn < 0 || Pn >= a.gc.n, podd = (p & 1) != 0;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const T cn = cxy(lci[J], r, flip);
+        clo[r] = podd ? chi[r] : clo[r];
+        chi[r] = cn;
+        const T v = podd ? (T)0.75 * clo[r] + (T)0.25 * chi[r] : (T)0.75 * chi[r] + (T)0.25 * clo[r];
+        U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
+      }
+    }
 #pragma unroll
     for (int s = 1; s <= NS; ++s) {
       const int zp = p - s;
