@@ -528,7 +528,7 @@ struct Exec {
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
     // the interpolation prologue loads the coarse columns under a tile, one per thread
-    if (PRO == PRO_INTERP && (!inpl || ((a.txw >> 1) + 3) * ((a.tyw >> 1) + 3) > NT))
+    if (PRO == PRO_INTERP && ((a.txw >> 1) + 3) * ((a.tyw >> 1) + 3) > NT)
       throw hip_error("internal: tile too wide for the interpolation prologue");
     a.nxcd = ns > 1 ? 1 : P->nxcd;
     int nt = a.ntx * a.nty * a.ntz;
@@ -552,15 +552,9 @@ struct Exec {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if constexpr (PRO == PRO_INTERP) {  // the interpolation prologue: in-place passes only
-      if (!inpl) throw hip_error("internal: interpolation prologue off the in-place path");
-      if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
-      else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
-    } else {
-      if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
-      else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
-      else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
-    }
+    if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
+    else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
+    else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
   }
 
   // can level l's segments be smoothed in place, one workgroup each, with
@@ -663,10 +657,10 @@ struct Exec {
     const T* dt = l > 0 ? H.t[l - 1] : nullptr;
     int st = 2 * nu;
     const bool boxp = st > 0 && P->fused && box_fits(l);
-    // the first in-place z pass forms the FMG interpolation itself, unless it
-    // is also the pass that restricts
-    const bool zint = pro == PRO_INTERP && !boxp && P->fused && st > 0 && seg_inplace(l) &&
-                      !(rmode >= 0 && st <= 2);
+    // the first z pass forms the FMG interpolation itself, unless it is also
+    // the pass that restricts
+    const bool zint = pro == PRO_INTERP && !boxp && P->fused && st > 0 &&
+                      !(seg_inplace(l) && rmode >= 0 && st <= 2);
     if (pro == PRO_INTERP && !zint) {
       interp(l);
       pro = PRO_LOAD;

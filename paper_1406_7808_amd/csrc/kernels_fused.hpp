@@ -78,8 +78,7 @@ template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_smooth_z(SmoothArgs<T> a) {
   constexpr int H = NS, NC = NT * RY;
-  static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT || (PRO == PRO_INTERP && RY == 2),
-                "interpolation prologue: in-place passes");
+  static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT || PRO == PRO_INTERP, "prologue");
   static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
   // neighbour exchange: per step parity, the idle class of the NS planes the
   // step's stages update (rank-indexed, see below)
