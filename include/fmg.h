@@ -107,7 +107,7 @@ int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *strea
  * 1/(6 + b_c) products and the order of a few sums); the batched interface
  * and the autotuner pick them per problem size.
  *   max_stages     half-sweeps per pass of the streaming smoother on levels
- *                  smoothed over two copies: 2 or 4 (default 2);
+ *                  smoothed over two copies: 2 or 4 (default 4);
  *   seg_inplace    1: segment levels whose compute region plus an 8-cell halo
  *                  fits 2048 columns are smoothed in place, one workgroup per
  *                  segment, 4 half-sweeps per pass (default 1);

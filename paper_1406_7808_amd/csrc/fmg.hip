@@ -218,7 +218,7 @@ struct fmg_plan {
   bool fused = true;          // temporally blocked smoother (else single-cell kernels)
   int Lc = 0;                 // global levels 0..Lc run in the persistent coarse kernel
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
-  int max_stages = 2;         // half-sweeps per temporally blocked launch (2 or 4)
+  int max_stages = 4;         // half-sweeps per temporally blocked launch (2 or 4)
   bool seg_inplace = true;    // segment levels: in place, one workgroup per segment
   bool use_box = true;        // segment levels whose box fits LDS: box-resident smoother
   std::set<const void*> lds_attr;  // kernels already allowed the whole LDS

@@ -89,8 +89,9 @@ def test_batch_rejects_bad_problem():
     assert e.value.status == fmg.FMG_EINVAL and "problem 1" in str(e.value)
 
 
-@pytest.mark.parametrize("kw", [dict(max_stages=4), dict(seg_inplace=0), dict(box=0),
-                                dict(target_blocks=256), dict(max_stages=4, seg_inplace=0, box=0)])
+@pytest.mark.parametrize("kw", [dict(max_stages=2), dict(seg_inplace=0), dict(box=0),
+                                dict(target_blocks=256), dict(max_stages=4, seg_inplace=0, box=0),
+                                dict(max_stages=2, seg_inplace=0, box=0)])
 def test_tuning_knobs_keep_the_solution(kw):
     print("tuning", kw, flush=True)
     N, L, K, S, J = 128, 7, 3, 4, [2, 4, 6]
