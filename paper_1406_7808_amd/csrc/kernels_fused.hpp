@@ -90,8 +90,9 @@ k_smooth_z(SmoothArgs<T> a) {
   __shared__ T ldsr[RES ? 2 : 1][RES ? NC : 1];
   __shared__ T lsf[RES ? NC : 1];
   __shared__ T invd[8];  // 1 / (6 + nb) for nb = 0..6 boundary faces
-  // interpolation prologue: the coarse plane under the tile, per step parity
-  __shared__ T lci[PRO == PRO_INTERP ? 2 : 1][PRO == PRO_INTERP ? NT : 1];
+  // interpolation and correction prologues: the coarse plane under the tile
+  // (u, or w - t), per step parity
+  __shared__ T lci[PRO != PRO_LOAD ? 2 : 1][PRO != PRO_LOAD ? NT : 1];
   __shared__ double lsu[RES ? NC : 1], lsr[RES ? NC : 1];
 
   const Geo gu = a.gu;
@@ -157,11 +158,12 @@ k_smooth_z(SmoothArgs<T> a) {
   // rhs from LDS)
   constexpr int NU = NS + 2, NF = NS + 1;
   T U[NU][RY], F[NF][RY];
-  T Qu[PF][RY], Qf[PF][RY], Qd[PF][RY], Qt[PF][RY];  // ring of planes in flight
+  T Qu[PF][RY], Qf[PF][RY];  // ring of planes in flight
   // interpolation prologue: this thread's coarse value of a fetched coarse
   // plane in the ring, and the xy-interpolated coarse planes lo and lo + 1 of
   // the current fine plane (lo = floor((p - 1) / 2))
-  T Qi[PF], clo[RY], chi[RY];
+  // (the correction prologue: this thread's w and t of the parent plane)
+  T Qi[PF], Qj[PF], clo[RY], chi[RY];
   // Columns are dealt to thread slots sorted by colour class: slots
   // [0, NC/2) hold the columns of one (x + y) parity, slots [NC/2, NC) the
   // other (txw is even, so every row has txw/2 of each).  In a half-sweep only
@@ -184,22 +186,22 @@ k_smooth_z(SmoothArgs<T> a) {
     return sl >= NC / 2 ? sl - NC / 2 : sl;
   };
   bool lact[RY];  // the slot's column is updated (inside C, not a tile edge)
-  // interpolation prologue: the tile's threads load the coarse columns under
-  // the tile, ctx x cty from (cX0, cY0), one each, into LDS.  Per slot: the
-  // LDS index of the coarse column (X0, Y0) under its column and, in ok bits
-  // 10-13, where X1 / Y1 lie: next (odd x / y) or previous, or reflected at a
-  // wall (X1 = X0, sign -1)
+  // interpolation and correction prologues: the tile's threads load the
+  // coarse columns under the tile, ctx x cty from (cX0, cY0), one each, into
+  // LDS.  Per slot: the LDS index of the coarse column (X0, Y0) under its
+  // column and, for the interpolation, in ok bits 10-13, where X1 / Y1 lie:
+  // next (odd x / y) or previous, or reflected at a wall (X1 = X0, sign -1)
   const int cX0 = ((ox - H) >> 1) - 1, cY0 = ((oy - H) >> 1) - 1;
   const int ctx = (txw >> 1) + 3, ctn = ctx * ((tyw >> 1) + 3);
   int tco = 0;  // this thread's coarse column (offset in the coarse box), if any
   bool tcv = false;
-  if (PRO == PRO_INTERP && (int)threadIdx.x < ctn) {
+  if (PRO != PRO_LOAD && (int)threadIdx.x < ctn) {
     const int X = cX0 + (int)threadIdx.x % ctx, Y = cY0 + (int)threadIdx.x / ctx;
     tcv = X >= 0 && X < a.gc.n && Y >= 0 && Y < a.gc.n && X >= Bc.o[0] && X < Bc.o[0] + a.gc.m &&
           Y >= Bc.o[1] && Y < Bc.o[1] + a.gc.m;
     tco = tcv ? (Y - Bc.o[1]) * a.gc.m + (X - Bc.o[0]) : 0;
   }
-  int io[PRO == PRO_INTERP ? RY : 1];
+  int io[PRO != PRO_LOAD ? RY : 1];
   unsigned ok[RY];  // bit0 stored xy, bit1 in C xy, bit2 output xy, bit3 not tile edge,
                     // bits 4-6 boundary faces in x and y, bit7 genuine, bit8 owns a
                     // coarse column (epilogue), bit9 cx odd
@@ -228,14 +230,15 @@ k_smooth_z(SmoothArgs<T> a) {
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
             (gen ? 128u : 0u) | (own ? 256u : 0u) | ((unsigned)(cx & 1) << 9);
     lact[r] = inc && inner;
-    if (PRO == PRO_INTERP) {
+    if (PRO != PRO_LOAD) {
       const int nc = a.gc.n, X0 = x >> 1, Y0 = y >> 1;
       const int X1 = (x & 1) ? X0 + 1 : X0 - 1, Y1 = (y & 1) ? Y0 + 1 : Y0 - 1;
       const bool rx = X1 < 0 || X1 >= nc, ry = Y1 < 0 || Y1 >= nc;
       // stored columns lie one coarse column inside the coarse tile on each side
       io[r] = st ? (Y0 - cY0) * ctx + (X0 - cX0) : ctx + 1;
-      ok[r] |= ((unsigned)(x & 1) << 10) | (rx ? 1u << 11 : 0u) | ((unsigned)(y & 1) << 12) |
-               (ry ? 1u << 13 : 0u);
+      if (PRO == PRO_INTERP)
+        ok[r] |= ((unsigned)(x & 1) << 10) | (rx ? 1u << 11 : 0u) | ((unsigned)(y & 1) << 12) |
+                 (ry ? 1u << 13 : 0u);
     }
     uo[r] = (y - B.o[1]) * gu.m + (x - B.o[0]);
 #pragma unroll
@@ -273,14 +276,19 @@ k_smooth_z(SmoothArgs<T> a) {
     const T c = (T)0.5625 * q0 + ((T)0.1875 * (s1 + s2) + (T)0.0625 * s3);
     return flip ? -c : c;
   };
-  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T(&qd)[RY], T(&qt)[RY], T& qi, unsigned& vu,
-                   unsigned& vf) {
+  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T& qi, T& qj, unsigned& vu, unsigned& vf) {
     if (PRO == PRO_INTERP) qi = fetch_c(((p - 1) >> 1) + 1);
+    if (PRO == PRO_CORRECT) {  // w and t of the parent plane (no reflection: parents lie inside)
+      const int P = p >> 1;
+      const bool v = tcv && P >= Bc.o[2] && P < Bc.o[2] + a.gc.m;
+      const long long ic = v ? (long long)(P - Bc.o[2]) * cmm + tco : 0;
+      qi = cd[ic];
+      qj = cdt[ic];
+    }
     const bool zs = p >= wlo[2] && p < whi[2];
     const bool zcin = p >= B.a[2] && p < B.b[2];
     const long long pu = (long long)(p - B.o[2]) * mm;
     const long long pr = (long long)(p - Br.o[2]) * rmm;
-    const long long pc = (long long)((p >> 1) - Bc.o[2]) * cmm;
     vu = 0;
     vf = 0;
 #pragma unroll
@@ -290,11 +298,6 @@ k_smooth_z(SmoothArgs<T> a) {
       vu |= (v ? 1u : 0u) << r;
       vf |= (w ? 1u : 0u) << r;
       if (PRO != PRO_INTERP) qu[r] = ub[v ? pu + uo[r] : 0];
-      if (PRO == PRO_CORRECT) {
-        const long long ic = v ? pc + ((ys[r] >> 1) - Bc.o[1]) * a.gc.m + ((xr[r] >> 1) - Bc.o[0]) : 0;
-        qd[r] = cd[ic];
-        qt[r] = cdt[ic];
-      }
       qf[r] = rb[w ? pr + (ys[r] - Br.o[1]) * a.gr.m + (xr[r] - Br.o[0]) : 0];
     }
   };
@@ -308,7 +311,7 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int r = 0; r < RY; ++r) clo[r] = chi[r] = cxy(lci[1], r, lo < 0 || lo >= a.gc.n);
   }
 #pragma unroll
-  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qd[k], Qt[k], Qi[k], Vu[k], Vf[k]);
+  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qi[k], Qj[k], Vu[k], Vf[k]);
   // step p0 + j with J = j & 1: the stages update the slots of half J
   auto step = [&](auto Jc, int p) {
     constexpr int J = decltype(Jc)::value, kq = J % PF;
@@ -320,17 +323,19 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int j = NF - 1; j > 0; --j)
 #pragma unroll
       for (int r = 0; r < RY; ++r) F[j][r] = F[j - 1][r];
-    const unsigned vuk = Vu[kq];  // U[0] of the interpolation prologue is formed after the exchange
+    // U[0] of the interpolation and correction prologues is formed after the
+    // exchange, from the coarse plane staged in LDS
+    const unsigned vuk = Vu[kq];
+    T uq[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      if (PRO != PRO_INTERP) {
-        const T v = PRO == PRO_CORRECT ? Qu[kq][r] + (Qd[kq][r] - Qt[kq][r]) : Qu[kq][r];
-        U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
-      }
+      if (PRO == PRO_LOAD) U[0][r] = ((vuk >> r) & 1u) ? Qu[kq][r] : (T)0;
+      uq[r] = Qu[kq][r];
       F[0][r] = ((Vf[kq] >> r) & 1u) ? Qf[kq][r] : (T)0;
     }
-    if (PRO == PRO_INTERP && (int)threadIdx.x < ctn) lci[J][threadIdx.x] = Qi[kq];
-    fetch(p + PF, Qu[kq], Qf[kq], Qd[kq], Qt[kq], Qi[kq], Vu[kq], Vf[kq]);
+    if (PRO != PRO_LOAD && (int)threadIdx.x < ctn)
+      lci[J][threadIdx.x] = PRO == PRO_CORRECT ? Qi[kq] - Qj[kq] : Qi[kq];
+    fetch(p + PF, Qu[kq], Qf[kq], Qi[kq], Qj[kq], Vu[kq], Vf[kq]);
     // NS half-sweeps as a wavefront: stage s applies half-sweep s (colour
     // (s - 1) & 1) to plane p - s.  Its cells read the other colour of that
     // plane as the previous step left it (no stage of this step changes it),
@@ -344,6 +349,10 @@ k_smooth_z(SmoothArgs<T> a) {
       for (int r = 0; r < RY; ++r)
         if (kbh(r) != J) lds[J][s - 1][rnk(r)] = U[s][r];
     __syncthreads();
+    if (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) U[0][r] = ((vuk >> r) & 1u) ? uq[r] + lci[J][io[r]] : (T)0;
+    }
     if (PRO == PRO_INTERP) {
       // plane p lies between coarse planes lo and lo + 1; lo advances on odd
       // p, and p takes 3/4 of the nearer one (FMG interpolation: trilinear,
