@@ -875,7 +875,8 @@ struct Exec {
     int L = P->L;
     H.f[L - 1] = const_cast<T*>(ftop);
     for (int l = 0; l < L; ++l) H.u[l] = H.ua[l];
-    for (int l = L - 1; l > 0; --l) {
+    // f hierarchy down to the coarse-level kernel's top (it restricts further)
+    for (int l = L - 1; l > P->Lc; --l) {
       int n = P->N >> (L - 1 - l);
       lvl = l;
       run("k_restrict_global", sizeof(T) * 1.125 * cube(n), grid_for(cube(n / 2), 1),

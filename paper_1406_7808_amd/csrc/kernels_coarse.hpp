@@ -7,8 +7,9 @@
 // (the top level's u and right-hand side, or the FMG right-hand sides), works
 // in LDS and writes back the top level's u, the only result used outside.
 // It performs either
-//   mode 0: FMG stages 0..top (Fig. 2 of the paper): u_0 = L_0^-1 f_0, then
-//           per level Pi, S^alpha and one FAS V-cycle with rhs f_l, or
+//   mode 0: FMG stages 0..top (Fig. 2 of the paper): f_top is restricted
+//           down to level 0, u_0 = L_0^-1 f_0, then per level Pi, S^alpha and
+//           one FAS V-cycle with rhs f_l, or
 //   mode 1: one FAS V-cycle (Fig. 1) on level top with right-hand side rt;
 //           with fas, rt holds the restricted residual of the level above and
 //           the kernel first forms the FAS right-hand side rt + L u (Eq. 4)
@@ -335,6 +336,23 @@ __device__ void blk_copy(T* lds, T* glob, int n) {
   }
 }
 
+// f of level l - 1 = R f of level l (mean of the 8 children, summed in FP64
+// in the order of the global restriction kernel); both plain, in LDS
+template <class T>
+__device__ void blk_restrict_f(const T* f, int n, T* fc) {
+  const int nc = n / 2, cnt = nc * nc * nc;
+  Walk3 w(threadIdx.x, blockDim.x, nc, nc, cnt);
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x, w.next()) {
+    double s = 0.0;
+    for (int k = 0; k < 2; ++k)
+      for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i)
+          s += (double)f[((2 * w.k + k) * n + (2 * w.j + j)) * n + (2 * w.i + i)];
+    fc[c] = (T)(s / 8.0);
+  }
+  __syncthreads();
+}
+
 // a level's solution (padded LDS) to an FP64 checkpoint array (n^3)
 template <class T>
 __device__ void blk_checkpoint(const T* lds, double* out, int n) {
@@ -377,14 +395,15 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   __syncthreads();
   for (int i = threadIdx.x; i < o.uend; i += blockDim.x) sm[i] = (T)0;  // halos
   __syncthreads();
-  if (g.mode == 0) {
-    for (int l = 0; l <= g.top; ++l)
-      blk_copy<T, true, false>(sm + o.f[l], const_cast<T*>(g.f[l]), g.n[l]);
+  if (g.mode == 0) {  // f of the top level; the coarser ones are restricted here
+    blk_copy<T, true, false>(sm + o.f[g.top], const_cast<T*>(g.f[g.top]), g.n[g.top]);
   } else {
     blk_copy<T, true, false>(sm + o.rt, const_cast<T*>(g.rt), g.n[g.top]);
     blk_copy<T, true, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);
   }
   __syncthreads();
+  if (g.mode == 0)
+    for (int l = g.top; l >= 1; --l) blk_restrict_f(sm + o.f[l], g.n[l], sm + o.f[l - 1]);
   if (g.mode == 1) {
     if (g.fas) blk_fas_rhs(sm + o.u[g.top], sm + o.rt, g.t[g.top], g.n[g.top]);
     blk_vcycle(sm, o, g, g.top, o.rt);
