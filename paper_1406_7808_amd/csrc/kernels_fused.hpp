@@ -303,7 +303,7 @@ k_smooth_z(SmoothArgs<T> a) {
   };
 
   if (threadIdx.x < 7) invd[threadIdx.x] = (T)1 / (T)(6 + (int)threadIdx.x);  // read after a barrier
-  if (PRO == PRO_INTERP) {  // the window starts with lo(p0) in both planes
+  if constexpr (PRO == PRO_INTERP) {  // the window starts with lo(p0) in both planes
     const int lo = (p0 - 1) >> 1;
     if ((int)threadIdx.x < ctn) lci[1][threadIdx.x] = fetch_c(lo);
     __syncthreads();
@@ -333,8 +333,9 @@ k_smooth_z(SmoothArgs<T> a) {
       uq[r] = Qu[kq][r];
       F[0][r] = ((Vf[kq] >> r) & 1u) ? Qf[kq][r] : (T)0;
     }
-    if (PRO != PRO_LOAD && (int)threadIdx.x < ctn)
-      lci[J][threadIdx.x] = PRO == PRO_CORRECT ? Qi[kq] - Qj[kq] : Qi[kq];
+    if constexpr (PRO != PRO_LOAD) {
+      if ((int)threadIdx.x < ctn) lci[J][threadIdx.x] = PRO == PRO_CORRECT ? Qi[kq] - Qj[kq] : Qi[kq];
+    }
     fetch(p + PF, Qu[kq], Qf[kq], Qi[kq], Qj[kq], Vu[kq], Vf[kq]);
     // NS half-sweeps as a wavefront: stage s applies half-sweep s (colour
     // (s - 1) & 1) to plane p - s.  Its cells read the other colour of that
@@ -349,11 +350,11 @@ k_smooth_z(SmoothArgs<T> a) {
       for (int r = 0; r < RY; ++r)
         if (kbh(r) != J) lds[J][s - 1][rnk(r)] = U[s][r];
     __syncthreads();
-    if (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
+    if constexpr (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
 #pragma unroll
       for (int r = 0; r < RY; ++r) U[0][r] = ((vuk >> r) & 1u) ? uq[r] + lci[J][io[r]] : (T)0;
     }
-    if (PRO == PRO_INTERP) {
+    if constexpr (PRO == PRO_INTERP) {
       // plane p lies between coarse planes lo and lo + 1; lo advances on odd
       // p, and p takes 3/4 of the nearer one (FMG interpolation: trilinear,
       // odd reflection at the walls)
@@ -413,11 +414,11 @@ k_smooth_z(SmoothArgs<T> a) {
     // are final), summed over the two fine planes of each coarse plane,
     // then over the 2 x 2 columns of each coarse cell
     const int zr = p - NS - 1;
-    if (RES) {  // every step: plane p - NS - 1 into the exchange of parity J
+    if constexpr (RES) {  // every step: plane p - NS - 1 into the exchange of parity J
 #pragma unroll
       for (int r = 0; r < RY; ++r) ldsr[J][threadIdx.x + NT * r] = U[NS + 1][r];
     }
-    if (RES && zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
+    if constexpr (RES) if (zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
       // slot sl's column at [sl]; pn: the slot of the same rank in the other half
       auto pnb = [&](int r) -> int {
         const int sl = threadIdx.x + NT * r;
@@ -465,7 +466,7 @@ k_smooth_z(SmoothArgs<T> a) {
         }
       }
     }
-    if (RES) {  // the rhs of plane p - NS, which the next step reduces
+    if constexpr (RES) {  // the rhs of plane p - NS, which the next step reduces
 #pragma unroll
       for (int r = 0; r < RY; ++r) lsf[threadIdx.x + NT * r] = F[NS][r];
     }
