@@ -615,7 +615,10 @@ struct Exec {
       throw hip_error("internal: FAS prologue needs the level's own right-hand side");
     double rd = PRO == PRO_CORRECT ? 1.25 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
-    if (a.fas) bytes += sizeof(T) * (c_cells(G) + st_cells(G));  // rhs and t written
+    if (a.fas) {  // rhs written on C, t on the parents of the finer level's stored cells
+      const long long tw = std::min<long long>(G.m, (a.gf.m + 1) / 2 + 1);
+      bytes += sizeof(T) * (c_cells(G) + (double)nseg(l) * tw * tw * tw);
+    }
     if (a.rmode >= 0)
       bytes += sizeof(T) * 2.0 * (a.rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
     run_shm(PRO == PRO_CORRECT ? "k_smooth_box<correct>" : "k_smooth_box<load>", bytes,

@@ -583,7 +583,8 @@ struct BoxArgs {
   // FAS prologue (fas > 0, load prologue only): the level was just restricted
   // into; rhs holds R res on F.  The kernel forms rhs = R res + L u on F and
   // L u on C \ F (Fig. 6; fas == 2: F is the whole region), writes it back
-  // over rhs, and writes t = the loaded box.
+  // over rhs, and writes t = the loaded box where the finer level's
+  // correction reads it (the parents of its stored cells).
   int fas;
   T* rhsw;  // = rhs, writable
   T* t;
@@ -666,9 +667,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   }
   // load the box (u, or u + P(d)) in batches of LB cells per thread, every
   // load of a batch in flight together (lanes outside the domain read element
-  // 0 and store 0); the FAS prologue also stores the loaded box as t, after
-  // the batch's LDS writes (a store ahead of them would hold each write back
-  // until it completes)
+  // 0 and store 0)
   constexpr int LB = PRO == PRO_LOAD ? kBoxLoads : kBoxLoadsCorrect;
   Walk3 wl(threadIdx.x, NT, m, m);
   for (int base = 0; base < mc; base += LB * NT) {
@@ -695,16 +694,30 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       const int c = base + threadIdx.x + r * NT;
       if (c < mc) bu[c] = vu[r];
     }
-    if (fas) {
-#pragma unroll
-      for (int r = 0; r < LB; ++r) {
-        const int c = base + threadIdx.x + r * NT;
-        if (c < mc) a.t[B.base + c] = vu[r];
-      }
-    }
+
   }
 
   __syncthreads();
+
+  // FAS prologue: t = the loaded box, where the finer level's correction reads
+  // it (the parents of the finer segment's stored cells, inside the domain)
+  if (fas) {
+    const Box Bf = seg_box(a.gf, q);
+    int tlo[3], tw[3];
+    for (int d = 0; d < 3; ++d) {
+      int lo = Bf.o[d] >> 1, hi = (Bf.o[d] + a.gf.m - 1) >> 1;
+      lo = max(max(lo, B.o[d]), 0);
+      hi = min(min(hi, B.o[d] + m - 1), n - 1);
+      tlo[d] = lo - B.o[d];
+      tw[d] = hi - lo + 1;
+    }
+    const int tc = tw[0] * tw[1] * tw[2];
+    Walk3 wt(threadIdx.x, NT, tw[0], tw[1], tc);
+    for (int c = threadIdx.x; c < tc; c += NT, wt.next()) {
+      const int l = ((tlo[2] + wt.k) * m + (tlo[1] + wt.j)) * m + (tlo[0] + wt.i);
+      a.t[B.base + l] = bu[l];
+    }
+  }
 
   const double s2 = (double)n * (double)n;
   // L u of the cell at LDS index l with nb boundary faces (Eq. 2, in FP64)
