@@ -566,7 +566,7 @@ constexpr int kBoxSlots = 8;  // cell pairs per thread
 // box cells per thread in flight while loading (bounded by registers: the
 // slots' right-hand sides are in flight too), fewer with the correction
 // prologue (three loads per cell)
-constexpr int kBoxLoads = 8;
+constexpr int kBoxLoads = 12;
 constexpr int kBoxLoadsCorrect = 6;
 
 template <class T>
