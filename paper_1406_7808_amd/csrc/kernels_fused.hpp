@@ -369,29 +369,42 @@ k_smooth_z(SmoothArgs<T> a) {
         U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
       }
     }
+    // the stages; INNER: all NS planes lie inside C and off the domain's z
+    // walls (most steps), so no stage tests its plane
+    auto stages = [&](auto INNERc) {
+      constexpr bool INNER = decltype(INNERc)::value;
 #pragma unroll
-    for (int s = 1; s <= NS; ++s) {
-      const int zp = p - s;
-      if (zp < B.a[2] || zp >= B.b[2]) continue;  // uniform over the block
-      const int nbz = (zp == 0) + (zp == n - 1);
+      for (int s = 1; s <= NS; ++s) {
+        const int zp = p - s;
+        int nbz = 0;
+        if constexpr (!INNER) {
+          if (zp < B.a[2] || zp >= B.b[2]) continue;  // uniform over the block
+          nbz = (zp == 0) + (zp == n - 1);
+        }
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        if (kbh(r) != J) continue;  // compile-time for RY = 2, per wavefront for RY = 1
-        // every lane of the slot computes; lanes whose column is not updated
-        // keep their value
-        // the stencil reads around the slot's rank, or around rank tw2 for
-        // columns that are never updated, so that every read is in bounds
-        const T* pl = lds[J][s - 1];
-        const int tw2 = txw >> 1, i = lact[r] ? rnk(r) : tw2;
-        const int xn = i - 1 + (int)((ok[r] >> 9) & 1u);
-        // the plane above (just updated by stage s - 1) is added last
-        const T sum = (((pl[xn] + pl[xn + 1]) + (pl[i - tw2] + pl[i + tw2])) + U[s + 1][r]) +
-                      U[s - 1][r];
-        const T inv = invd[(int)((ok[r] >> 4) & 7u) + nbz];
-        const T nv = (sum - a.h2 * F[s][r]) * inv;
-        U[s][r] = lact[r] ? nv : U[s][r];
+        for (int r = 0; r < RY; ++r) {
+          if (kbh(r) != J) continue;  // compile-time for RY = 2, per wavefront for RY = 1
+          // every lane of the slot computes; lanes whose column is not updated
+          // keep their value
+          // the stencil reads around the slot's rank, or around rank tw2 for
+          // columns that are never updated, so that every read is in bounds
+          const T* pl = lds[J][s - 1];
+          const int tw2 = txw >> 1, i = lact[r] ? rnk(r) : tw2;
+          const int xn = i - 1 + (int)((ok[r] >> 9) & 1u);
+          // the plane above (just updated by stage s - 1) is added last
+          const T sum = (((pl[xn] + pl[xn + 1]) + (pl[i - tw2] + pl[i + tw2])) + U[s + 1][r]) +
+                        U[s - 1][r];
+          const T inv = invd[(int)((ok[r] >> 4) & 7u) + nbz];
+          const T nv = (sum - a.h2 * F[s][r]) * inv;
+          U[s][r] = lact[r] ? nv : U[s][r];
+        }
       }
-    }
+    };
+    // (kernels held to 64 registers for two workgroups per CU keep one path)
+    if (WPE < 8 && p - NS >= B.a[2] && p - 1 < B.b[2] && p - NS >= 1 && p - 1 <= n - 2)
+      stages(std::integral_constant<bool, WPE < 8>{});
+    else
+      stages(std::false_type{});
     // plane p - NS is final
     const int zo = p - NS;
     if (a.outmode) {  // genuine cells to the caller's solution
