@@ -85,15 +85,16 @@ k_smooth_z(SmoothArgs<T> a) {
   __shared__ T lds[2][NS][NC / 2];
   // epilogue: exchange of the plane being reduced (per step parity: the
   // previous step's is the plane below), each column's rhs of that plane, and
-  // per-column sums over the two fine planes of a coarse plane (indexed by
-  // slot: each half holds one class by rank, as in the stages)
+  // per-column sums over the two fine planes of a coarse plane, per coarse
+  // plane parity (indexed by slot: each half holds one class by rank, as in
+  // the stages)
   __shared__ T ldsr[RES ? 2 : 1][RES ? NC : 1];
   __shared__ T lsf[RES ? NC : 1];
   __shared__ T invd[8];  // 1 / (6 + nb) for nb = 0..6 boundary faces
   // interpolation and correction prologues: the coarse plane under the tile
   // (u, or w - t), per step parity
   __shared__ T lci[PRO != PRO_LOAD ? 2 : 1][PRO != PRO_LOAD ? NT : 1];
-  __shared__ double lsu[RES ? NC : 1], lsr[RES ? NC : 1];
+  __shared__ double lsu[RES ? 2 : 1][RES ? NC : 1], lsr[RES ? 2 : 1][RES ? NC : 1];
 
   const Geo gu = a.gu;
   const int q = blockIdx.y;
@@ -136,9 +137,11 @@ k_smooth_z(SmoothArgs<T> a) {
   const long long mm = (long long)gu.m * gu.m;
 
   // steps p0..p1, padded to an even count (steps run in pairs): the padding
-  // step only touches planes past the chunk, whose results are never stored
+  // step only touches planes past the chunk, whose results are never stored.
+  // The epilogue trails the last plane by two steps (residual, then the
+  // coarse cells of the last coarse plane).
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
-  const int p0 = oz - NS, p1 = zs1 - 1 + NS + RES;
+  const int p0 = oz - NS, p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box(a.gr, q);
@@ -349,6 +352,10 @@ k_smooth_z(SmoothArgs<T> a) {
 #pragma unroll
       for (int r = 0; r < RY; ++r)
         if (kbh(r) != J) lds[J][s - 1][rnk(r)] = U[s][r];
+    if constexpr (RES) {  // the epilogue's plane p - NS - 1 (final since the last step)
+#pragma unroll
+      for (int r = 0; r < RY; ++r) ldsr[J][threadIdx.x + NT * r] = U[NS + 1][r];
+    }
     __syncthreads();
     if constexpr (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
 #pragma unroll
@@ -424,29 +431,54 @@ k_smooth_z(SmoothArgs<T> a) {
         if (ok[r] & 4u) wb[pw + uo[r]] = U[NS][r];
     }
     // epilogue: residual of plane zr = p - NS - 1 (its neighbours zr +- 1
-    // are final), summed over the two fine planes of each coarse plane,
-    // then over the 2 x 2 columns of each coarse cell
+    // are final), summed over the two fine planes of each coarse plane, then,
+    // one step later, over the 2 x 2 columns of each coarse cell.  Every LDS
+    // value it reads from other slots was written before this step's
+    // exchange barrier: the plane zr in the exchange of parity J, and the
+    // sums of coarse plane (zr - 1) / 2, complete at the last step, in the
+    // buffer of its parity.  Each is rewritten two steps later at the
+    // earliest, after the next step's barrier.
     const int zr = p - NS - 1;
-    if constexpr (RES) {  // every step: plane p - NS - 1 into the exchange of parity J
+    // slot sl's column at [sl]; pn: the slot of the same rank in the other half
+    auto pnb = [&](int r) -> int {
+      const int sl = threadIdx.x + NT * r;
+      return sl >= NC / 2 ? sl - NC / 2 : sl + NC / 2;
+    };
+    if constexpr (RES) if (((zr - 1) & 1) && zr - 1 >= B.a[2] && zr - 1 < B.b[2]) {
+      // coarse plane (zr - 1) / 2 (uniform over the block); C starts on an even plane
+      const int zc = (zr - 1) >> 1, cb = zc & 1;
+      const bool zt = a.rmode == 0 || (zr - 1 >= gz0 && zr - 1 < gz0 + gu.g);
+      const Box Bo = seg_box(a.gcr, q);
 #pragma unroll
-      for (int r = 0; r < RY; ++r) ldsr[J][threadIdx.x + NT * r] = U[NS + 1][r];
+      for (int r = 0; r < RY; ++r) {
+        if (zt && (ok[r] & 256u)) {
+          // the 2 x 2 columns (cx, cy) .. (cx + 1, cy + 1): this slot, the
+          // other half at ranks + (cx & 1) and + txw/2, and this half at
+          // rank + txw/2 + (cx & 1)
+          const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
+          const int od = (int)((ok[r] >> 9) & 1u);
+          const double* su = lsu[cb];
+          const double* sr = lsr[cb];
+          const double tu = (su[sl] + su[pn + od]) + (su[pn + tw2] + su[sl + tw2 + od]);
+          const double tr = (sr[sl] + sr[pn + od]) + (sr[pn + tw2] + sr[sl + tw2 + od]);
+          const long long id = at(a.gcr, Bo, xr[r] >> 1, ys[r] >> 1, zc);
+          a.uc[id] = (T)(tu / 8.0);
+          a.rc[id] = (T)(tr / 8.0);
+        }
+      }
     }
     if constexpr (RES) if (zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
-      // slot sl's column at [sl]; pn: the slot of the same rank in the other half
-      auto pnb = [&](int r) -> int {
-        const int sl = threadIdx.x + NT * r;
-        return sl >= NC / 2 ? sl - NC / 2 : sl + NC / 2;
-      };
-      __syncthreads();
       const unsigned nbz = (zr == 0) + (zr == n - 1);
       const double s2 = (double)n * (double)n;
-      const bool odd = zr & 1;  // C starts on an even plane
+      const bool odd = zr & 1;
+      const int cb = (zr >> 1) & 1;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (ok[r] & 2u) {  // C lies NS columns inside the tile: neighbours are in it
           const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
           const int xn = pn - 1 + (int)((ok[r] >> 9) & 1u);
           const T* pl = ldsr[J];
+          // the plane below is this slot's own entry of the previous step
           const double sn = (((double)pl[xn] + (double)pl[xn + 1]) +
                              ((double)pl[pn - tw2] + (double)pl[pn + tw2])) +
                             ((double)ldsr[J ^ 1][sl] + (double)U[NS][r]);
@@ -454,28 +486,8 @@ k_smooth_z(SmoothArgs<T> a) {
           const double nb = (double)(6u + ((ok[r] >> 4) & 7u) + nbz);
           const double res = (double)lsf[sl] - (sn - nb * uv) * s2;
           // the column's sums over the two fine planes, kept in its own LDS entry
-          lsu[sl] = odd ? lsu[sl] + uv : uv;
-          lsr[sl] = odd ? lsr[sl] + res : res;
-        }
-      }
-      if (odd) {
-        __syncthreads();
-        const bool zt = a.rmode == 0 || (zr >= gz0 && zr < gz0 + gu.g);
-        const Box Bo = seg_box(a.gcr, q);
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-          if (zt && (ok[r] & 256u)) {
-            // the 2 x 2 columns (cx, cy) .. (cx + 1, cy + 1): this slot, the
-            // other half at ranks + (cx & 1) and + txw/2, and this half at
-            // rank + txw/2 + (cx & 1)
-            const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
-            const int od = (int)((ok[r] >> 9) & 1u);
-            const double tu = (lsu[sl] + lsu[pn + od]) + (lsu[pn + tw2] + lsu[sl + tw2 + od]);
-            const double tr = (lsr[sl] + lsr[pn + od]) + (lsr[pn + tw2] + lsr[sl + tw2 + od]);
-            const long long id = at(a.gcr, Bo, xr[r] >> 1, ys[r] >> 1, zr >> 1);
-            a.uc[id] = (T)(tu / 8.0);
-            a.rc[id] = (T)(tr / 8.0);
-          }
+          lsu[cb][sl] = odd ? lsu[cb][sl] + uv : uv;
+          lsr[cb][sl] = odd ? lsr[cb][sl] + res : res;
         }
       }
     }
