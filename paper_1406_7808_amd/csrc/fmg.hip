@@ -305,6 +305,12 @@ static dim3 grid_for(long long cells, int nseg) {
 template <int NS>
 constexpr int kPrefetch = 1;
 
+// Two-copy passes on levels of edge up to kLatencyEdge run few, short z
+// marches whose every plane comes from beyond the L2: they take one column
+// per thread and keep two planes in flight, so a step's loads have two steps
+// to arrive (four in flight were slower)
+constexpr int kLatencyEdge = 64;
+
 template <class X>
 static bool nonnull(const X&) { return true; }
 template <class X>
@@ -341,13 +347,14 @@ static bool nonnull(const CoarseArgs<X>& a) {
 }
 
 // profile label of one k_smooth_z instantiation, e.g. "k_smooth_z<load,ns2,ry1>"
-template <int NS, int PRO, int RY, int RES>
+template <int NS, int PRO, int RY, int RES, int PF>
 static const char* zlabel() {
   static const std::string s = std::string("k_smooth_z<") +
                                (PRO == PRO_CORRECT ? "correct" : PRO == PRO_INTERP ? "interp" : "load") +
                                ",ns" +
                                std::to_string(NS) + ",ry" + std::to_string(RY) +
-                               (RES ? ",res" : "") + ">";
+                               (RES ? ",res" : "") + (PF > 1 ? ",pf" + std::to_string(PF) : "") +
+                               ">";
   return s.c_str();
 }
 
@@ -452,13 +459,14 @@ struct Exec {
 
   // one temporally blocked launch of NS half-sweeps with prologue PRO; RY
   // columns per thread; inpl: one workgroup per segment, updated in place
-  template <int NS, int RY, int PRO, int RES = 0>
+  template <int NS, int RY, int PRO, int RES = 0, int PF = kPrefetch<NS>>
   void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl,
                 double* out = nullptr, int outmode = 0, int rmode = -1) {
     constexpr int NT = 1024, NC = NT * RY;
     // two workgroups per CU (at most 64 VGPRs) where the kernel fits them
+    // (not the latency variant: its launches are small)
     constexpr int WPE =
-        (NS <= 2 && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD && !RES))) ? 8 : 4;
+        (PF == 1 && NS <= 2 && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD && !RES))) ? 8 : 4;
     const Geo& G = H.geo[l];
     if (PRO != PRO_LOAD && (!c || !ct)) throw hip_error("internal: null coarse increment");
     SmoothArgs<T> a{};
@@ -541,8 +549,8 @@ struct Exec {
       bytes += 8.0 * outmode * cube(P->N) - sizeof(T) * c_cells(G);
     if (RES)  // uc and rc on the coarse target
       bytes += 2.0 * sizeof(T) * (rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
-    run(zlabel<NS, PRO, RY, RES>(), bytes,
-        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, kPrefetch<NS>, WPE, RES>,
+    run(zlabel<NS, PRO, RY, RES, PF>(), bytes,
+        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, PF, WPE, RES>,
         a);
   }
 
@@ -552,7 +560,10 @@ struct Exec {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
+    if (!inpl && H.geo[l].n <= kLatencyEdge) {
+      if (ns == 2) smooth_z<2, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
+      else smooth_z<4, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
+    } else if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
     else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
     else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
   }
