@@ -483,8 +483,9 @@ struct Exec {
     if (outmode && (!inpl || !out)) throw hip_error("internal: output epilogue needs an in-place pass");
     a.out = out;
     a.outmode = outmode;
-    if (RES != (rmode >= 0) || (RES && (!inpl || l < 1)))
-      throw hip_error("internal: residual epilogue needs an in-place pass");
+    // over two copies the output columns are the whole level: global levels only
+    if (RES != (rmode >= 0) || (RES && (l < 1 || (!inpl && (rmode != 0 || G.ghost)))))
+      throw hip_error("internal: residual epilogue without a coarse target");
     a.rmode = rmode;
     a.uc = RES ? H.u[l - 1] : nullptr;
     a.rc = RES ? H.rhs[l - 1] : nullptr;
@@ -504,15 +505,17 @@ struct Exec {
       // every stored cell inside the domain is written, so the new copy is whole
       int wext = cext(l) + 2 * G.ghost;
       if (wext > G.n) wext = G.n;
+      // tile halo: NS columns, one more for the residual epilogue
+      constexpr int HH = NS + RES;
       // tile shape: the fewest loaded columns covering the write region
       long long best = -1;
       // even widths: the kernel deals each row's columns to two colour classes
-      for (int tx = 2 * NS + 2; tx <= 256 && tx * (2 * NS + 2) <= NC; tx += 2) {
+      for (int tx = 2 * HH + 2; tx <= 256 && tx * (2 * HH + 2) <= NC; tx += 2) {
         int ty = NC / tx;
-        if (ty > wext + 2 * NS) ty = wext + 2 * NS;
-        if (ty < 2 * NS + 2) continue;
-        long long cost = (long long)((wext + tx - 2 * NS - 1) / (tx - 2 * NS)) *
-                         ((wext + ty - 2 * NS - 1) / (ty - 2 * NS)) * tx * ty;
+        if (ty > wext + 2 * HH) ty = wext + 2 * HH;
+        if (ty < 2 * HH + 2) continue;
+        long long cost = (long long)((wext + tx - 2 * HH - 1) / (tx - 2 * HH)) *
+                         ((wext + ty - 2 * HH - 1) / (ty - 2 * HH)) * tx * ty;
         if (tx < 16) cost += cost / 4;  // short rows load poorly
         if (best < 0 || cost < best) {
           best = cost;
@@ -520,7 +523,7 @@ struct Exec {
           a.tyw = ty;
         }
       }
-      const int SX = a.txw - 2 * NS, SY = a.tyw - 2 * NS;
+      const int SX = a.txw - 2 * HH, SY = a.tyw - 2 * HH;
       a.ntx = (wext + SX - 1) / SX;
       a.nty = (wext + SY - 1) / SY;
       long long bxy = (long long)a.ntx * a.nty * ns;
@@ -532,6 +535,7 @@ struct Exec {
       if (ntz > zmax) ntz = zmax;
       if (ntz < 1) ntz = 1;
       a.zc = (wext + ntz - 1) / ntz;
+      if (RES) a.zc += a.zc & 1;  // chunks hold whole coarse planes
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
@@ -709,6 +713,12 @@ struct Exec {
         // the last pass of a pre-smoothing also restricts (residual epilogue)
         smooth_z<2, 2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, true, nullptr, 0, rmode);
         restricted = true;
+      } else if (pr == PRO_LOAD && rmode == 0 && !inpl && !G.ghost && st == ns &&
+                 G.n <= kLatencyEdge) {
+        // ... and over two copies on the small global levels
+        if (ns == 2) smooth_z<2, 1, PRO_LOAD, 1, 2>(l, rhs, gr, d, dt, Gc, false, nullptr, 0, 0);
+        else smooth_z<4, 1, PRO_LOAD, 1, 2>(l, rhs, gr, d, dt, Gc, false, nullptr, 0, 0);
+        restricted = true;
       } else if (pr == PRO_CORRECT) {
         smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       } else if (pr == PRO_INTERP) {
@@ -836,19 +846,21 @@ struct Exec {
   }
 
   // FAS V-cycle on global level l with right-hand side rhs (Fig. 1)
-  // presmoothed: S^nu1 has already been applied (fused with the FMG step)
+  // presmoothed: S^nu1 has already been applied (fused with the FMG step),
+  // and restricted tells whether that pass also restricted
   // fas: rhs holds the restricted residual only, the coarse kernel forms the
   // FAS right-hand side (levels up to Lc)
-  void vcycle_global(int l, const T* rhs, bool presmoothed = false, bool fas = false) {
+  void vcycle_global(int l, const T* rhs, bool presmoothed = false, bool fas = false,
+                     bool restricted = false) {
     if (l <= P->Lc) {
       coarse(l, 1, rhs, fas ? 1 : 0);
       return;
     }
     if (fas) throw hip_error("internal: deferred FAS right-hand side above the coarse levels");
     const Geo& G = H.geo[l];
-    if (!presmoothed) smooth(l, rhs, G, P->nu1);
+    if (!presmoothed) restricted = smooth(l, rhs, G, P->nu1, PRO_LOAD, 0, 0);
     const bool cf = l - 1 <= P->Lc;
-    descend(l, rhs, G, 0, 1, false, cf);
+    descend(l, rhs, G, 0, 1, restricted, cf);
     vcycle_global(l - 1, H.rhs[l - 1], false, cf);
     smooth(l, rhs, G, P->nu2, PRO_CORRECT);
   }
@@ -905,8 +917,8 @@ struct Exec {
       const Geo& G = H.geo[l];
       // Pi, S^alpha and the V-cycle's S^nu1 form one fused pass
       if (l <= P->T) {
-        smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP);
-        vcycle_global(l, H.f[l], true);
+        bool r = smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP, 0, 0);
+        vcycle_global(l, H.f[l], true, false, r);
       } else {
         const int rmode = (l - 1 > P->T) ? 0 : 1;
         bool r = smooth(l, H.f[l], global_geo(G.n), P->alpha + P->nu1, PRO_INTERP, 0, rmode);

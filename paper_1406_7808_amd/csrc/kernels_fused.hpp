@@ -77,7 +77,7 @@ struct SmoothArgs {
 template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_smooth_z(SmoothArgs<T> a) {
-  constexpr int H = NS, NC = NT * RY;
+  constexpr int NC = NT * RY;
   static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT || PRO == PRO_INTERP, "prologue");
   static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
   // neighbour exchange: per step parity, the idle class of the NS planes the
@@ -100,6 +100,10 @@ k_smooth_z(SmoothArgs<T> a) {
   const int q = blockIdx.y;
   const Box B = seg_box(gu, q);
   const int n = gu.n;
+  const bool inpl = a.inplace != 0;
+  // tile halo: NS columns; a residual over two copies needs the neighbours of
+  // the output columns final too, one more
+  const int H = NS + (RES && !inpl ? 1 : 0);
   const int txw = a.txw, tyw = a.tyw, sx = txw - 2 * H, sy = tyw - 2 * H;
   // blocks are dealt round-robin to the L2 domains: give each domain a
   // contiguous range of tiles so neighbouring tiles share an L2
@@ -116,7 +120,6 @@ k_smooth_z(SmoothArgs<T> a) {
   // load region: every stored cell inside the domain.  The tiles partition
   // the load region (two copies) or C (in place); in place, a correction
   // also stores the ghost layer around C.
-  const bool inpl = a.inplace != 0;
   int wlo[3], whi[3], glo[3], ghi[3];
   for (int d = 0; d < 3; ++d) {
     wlo[d] = B.o[d] < 0 ? 0 : B.o[d];
@@ -141,7 +144,9 @@ k_smooth_z(SmoothArgs<T> a) {
   // The epilogue trails the last plane by two steps (residual, then the
   // coarse cells of the last coarse plane).
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
-  const int p0 = oz - NS, p1 = zs1 - 1 + NS + 2 * RES;
+  // (over two copies the march starts one plane lower, so that the plane
+  // below the chunk is final for its residual too)
+  const int p0 = oz - NS - (RES && !inpl ? 1 : 0), p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box(a.gr, q);
@@ -227,8 +232,9 @@ k_smooth_z(SmoothArgs<T> a) {
     const bool inner = col && cx > 0 && cx < txw - 1 && cy > 0 && cy < tyw - 1;
     const unsigned nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
     const bool gen = col && x >= gx0 && x < gx0 + gu.g && y >= gy0 && y < gy0 + gu.g;
-    // epilogue: the column holding child (0,0) of a coarse target cell
-    const bool own = RES && (a.rmode == 0 ? inc && ((x - B.a[0]) & 1) == 0 && ((y - B.a[1]) & 1) == 0
+    // epilogue: the column holding child (0,0) of a coarse target cell (the
+    // output columns are C in place)
+    const bool own = RES && (a.rmode == 0 ? outp && ((x - B.a[0]) & 1) == 0 && ((y - B.a[1]) & 1) == 0
                                           : gen && (x & 1) == 0 && (y & 1) == 0);
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
             (gen ? 128u : 0u) | (own ? 256u : 0u) | ((unsigned)(cx & 1) << 9);
@@ -444,8 +450,8 @@ k_smooth_z(SmoothArgs<T> a) {
       const int sl = threadIdx.x + NT * r;
       return sl >= NC / 2 ? sl - NC / 2 : sl + NC / 2;
     };
-    if constexpr (RES) if (((zr - 1) & 1) && zr - 1 >= B.a[2] && zr - 1 < B.b[2]) {
-      // coarse plane (zr - 1) / 2 (uniform over the block); C starts on an even plane
+    if constexpr (RES) if (((zr - 1) & 1) && zr - 1 >= oz && zr - 1 < oz1) {
+      // coarse plane (zr - 1) / 2 (uniform over the block)
       const int zc = (zr - 1) >> 1, cb = zc & 1;
       const bool zt = a.rmode == 0 || (zr - 1 >= gz0 && zr - 1 < gz0 + gu.g);
       const Box Bo = seg_box(a.gcr, q);
@@ -467,14 +473,15 @@ k_smooth_z(SmoothArgs<T> a) {
         }
       }
     }
-    if constexpr (RES) if (zr >= B.a[2] && zr < B.b[2]) {  // uniform over the block
+    // (the chunk's planes [oz, oz1) are C in place; chunks start on an even plane)
+    if constexpr (RES) if (zr >= oz && zr < oz1) {  // uniform over the block
       const unsigned nbz = (zr == 0) + (zr == n - 1);
       const double s2 = (double)n * (double)n;
       const bool odd = zr & 1;
       const int cb = (zr >> 1) & 1;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        if (ok[r] & 2u) {  // C lies NS columns inside the tile: neighbours are in it
+        if (ok[r] & 4u) {  // output columns lie H inside the tile: neighbours are in it
           const int sl = threadIdx.x + NT * r, pn = pnb(r), tw2 = txw >> 1;
           const int xn = pn - 1 + (int)((ok[r] >> 9) & 1u);
           const T* pl = ldsr[J];
