@@ -27,6 +27,7 @@
 #include "../../include/fmg.h"
 #include "grid.hpp"
 #include "kernels_coarse.hpp"
+#include "kernels_cols.hpp"
 #include "kernels_descend.hpp"
 #include "kernels_fused.hpp"
 #include "kernels_norms.hpp"
@@ -305,9 +306,11 @@ static dim3 grid_for(long long cells, int nseg) {
 template <int NS>
 constexpr int kPrefetch = 1;
 
-// Two-copy passes on levels of edge up to kLatencyEdge run few, short z
-// marches whose every plane comes from beyond the L2: they take one column
-// per thread and keep two planes in flight, so a step's loads have two steps
+// Two-copy passes on levels of edge up to kLatencyEdge are chains of memory
+// round trips rather than streams.  On global levels they run in the column
+// smoother, which loads a whole z chunk at once; on segment levels (reached
+// only with the box and in-place smoothers off) the z march takes one column
+// per thread and keeps two planes in flight, so a step's loads have two steps
 // to arrive (four in flight were slower)
 constexpr int kLatencyEdge = 64;
 
@@ -355,6 +358,15 @@ static const char* zlabel() {
                                std::to_string(NS) + ",ry" + std::to_string(RY) +
                                (RES ? ",res" : "") + (PF > 1 ? ",pf" + std::to_string(PF) : "") +
                                ">";
+  return s.c_str();
+}
+
+// profile label of one k_smooth_cols instantiation, e.g. "k_smooth_cols<load,ns4,res>"
+template <int NS, int PRO, int RES>
+static const char* clabel() {
+  static const std::string s = std::string("k_smooth_cols<") +
+                               (PRO == PRO_CORRECT ? "correct" : PRO == PRO_INTERP ? "interp" : "load") +
+                               ",ns" + std::to_string(NS) + (RES ? ",res" : "") + ">";
   return s.c_str();
 }
 
@@ -483,9 +495,8 @@ struct Exec {
     if (outmode && (!inpl || !out)) throw hip_error("internal: output epilogue needs an in-place pass");
     a.out = out;
     a.outmode = outmode;
-    // over two copies the output columns are the whole level: global levels only
-    if (RES != (rmode >= 0) || (RES && (l < 1 || (!inpl && (rmode != 0 || G.ghost)))))
-      throw hip_error("internal: residual epilogue without a coarse target");
+    if (RES != (rmode >= 0) || (RES && (!inpl || l < 1)))
+      throw hip_error("internal: residual epilogue needs an in-place pass");
     a.rmode = rmode;
     a.uc = RES ? H.u[l - 1] : nullptr;
     a.rc = RES ? H.rhs[l - 1] : nullptr;
@@ -505,8 +516,7 @@ struct Exec {
       // every stored cell inside the domain is written, so the new copy is whole
       int wext = cext(l) + 2 * G.ghost;
       if (wext > G.n) wext = G.n;
-      // tile halo: NS columns, one more for the residual epilogue
-      constexpr int HH = NS + RES;
+      constexpr int HH = NS;  // tile halo
       // tile shape: the fewest loaded columns covering the write region
       long long best = -1;
       // even widths: the kernel deals each row's columns to two colour classes
@@ -535,7 +545,6 @@ struct Exec {
       if (ntz > zmax) ntz = zmax;
       if (ntz < 1) ntz = 1;
       a.zc = (wext + ntz - 1) / ntz;
-      if (RES) a.zc += a.zc & 1;  // chunks hold whole coarse planes
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
@@ -558,13 +567,77 @@ struct Exec {
         a);
   }
 
+  // NS half-sweeps with prologue PRO on a small global level, one column
+  // per thread with its whole z chunk in registers (two copies); RES: the
+  // pass also restricts u and the residual to level l - 1
+  template <int NS, int PRO, int RES>
+  void smooth_cols(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc) {
+    constexpr int NT = 1024, ZC = 2, HH = NS + RES;
+    const Geo& G = H.geo[l];
+    const int n = G.n;
+    if (G.ghost || nseg(l) != 1 || (RES && l < 1))
+      throw hip_error("internal: the column smoother takes global levels");
+    if (PRO != PRO_LOAD && (!c || (PRO == PRO_CORRECT && !ct)))
+      throw hip_error("internal: null coarse increment");
+    SmoothArgs<T> a{};
+    a.uin = H.u[l];
+    a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
+    a.gu = G;
+    H.u[l] = a.u;  // the written copy becomes current
+    a.rhs = rhs;
+    a.gr = gr;
+    a.c = c;
+    a.ct = ct;
+    a.gc = gc;
+    a.inplace = 0;
+    a.rmode = RES ? 0 : -1;
+    a.uc = RES ? H.u[l - 1] : nullptr;
+    a.rc = RES ? H.rhs[l - 1] : nullptr;
+    a.gcr = H.geo[l > 0 ? l - 1 : 0];
+    const double h = 1.0 / (double)n;
+    a.h2 = (T)(h * h);
+    // tile shape: the fewest loaded columns covering the level; even extents,
+    // so that every output region starts on even x and y
+    long long best = -1;
+    for (int tx = 2 * HH + 2; tx <= 256 && tx * (2 * HH + 2) <= NT; tx += 2) {
+      int ty = NT / tx;
+      if (ty > n + 2 * HH) ty = n + 2 * HH;
+      ty &= ~1;
+      if (ty < 2 * HH + 2) continue;
+      long long cost = (long long)((n + tx - 2 * HH - 1) / (tx - 2 * HH)) *
+                       ((n + ty - 2 * HH - 1) / (ty - 2 * HH)) * tx * ty;
+      if (best < 0 || cost < best) {
+        best = cost;
+        a.txw = tx;
+        a.tyw = ty;
+      }
+    }
+    // (the restriction pairs cells: even edges only)
+    if (best < 0 || (RES && (n & 1))) throw hip_error("internal: no tile for the column smoother");
+    a.ntx = (n + a.txw - 2 * HH - 1) / (a.txw - 2 * HH);
+    a.nty = (n + a.tyw - 2 * HH - 1) / (a.tyw - 2 * HH);
+    a.ntz = (n + ZC - 1) / ZC;
+    a.zc = ZC;
+    a.nxcd = P->nxcd;
+    const int nt = a.ntx * a.nty * a.ntz;
+    const int per = (nt + a.nxcd - 1) / a.nxcd;
+    double rd = PRO == PRO_CORRECT ? 1.25 : PRO == PRO_INTERP ? 0.125 : 1.0;
+    double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
+    if (RES) bytes += 2.0 * sizeof(T) * c_cells(G) / 8.0;
+    run(clabel<NS, PRO, RES>(), bytes, dim3(per * a.nxcd), dim3(NT),
+        k_smooth_cols<T, NS, PRO, RES, ZC>, a);
+  }
+
   template <int PRO>
   void smooth_z_ns(int ns, bool inpl, int l, const T* rhs, Geo gr, const T* c, const T* ct,
                    Geo gc, double* out = nullptr, int outmode = 0) {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if (!inpl && H.geo[l].n <= kLatencyEdge) {
+    if (!inpl && !H.geo[l].ghost && H.geo[l].n <= kLatencyEdge) {
+      if (ns == 2) smooth_cols<2, PRO, 0>(l, rhs, gr, c, ct, gc);
+      else smooth_cols<4, PRO, 0>(l, rhs, gr, c, ct, gc);
+    } else if (!inpl && H.geo[l].n <= kLatencyEdge) {
       if (ns == 2) smooth_z<2, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
       else smooth_z<4, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
     } else if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
@@ -716,8 +789,8 @@ struct Exec {
       } else if (pr == PRO_LOAD && rmode == 0 && !inpl && !G.ghost && st == ns &&
                  G.n <= kLatencyEdge) {
         // ... and over two copies on the small global levels
-        if (ns == 2) smooth_z<2, 1, PRO_LOAD, 1, 2>(l, rhs, gr, d, dt, Gc, false, nullptr, 0, 0);
-        else smooth_z<4, 1, PRO_LOAD, 1, 2>(l, rhs, gr, d, dt, Gc, false, nullptr, 0, 0);
+        if (ns == 2) smooth_cols<2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc);
+        else smooth_cols<4, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc);
         restricted = true;
       } else if (pr == PRO_CORRECT) {
         smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);

@@ -336,6 +336,35 @@ __device__ void blk_copy(T* lds, T* glob, int n) {
   }
 }
 
+// the right-hand side (plain) and u (padded) of an n^3 level from global
+// memory into LDS, all loads of both issued before the stores
+template <class T>
+__device__ void blk_load_rhs_u(T* lr, const T* gr, T* lu, const T* gu, int n) {
+  const int cnt = n * n * n, NT = blockDim.x;
+  Walk3 w(threadIdx.x, NT, n, n, cnt);
+  for (int base = 0; base < cnt; base += 4 * NT) {
+    T vr[4], vu[4];
+    int li[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = base + threadIdx.x + k * NT;
+      const bool in = i < cnt;
+      li[k] = in ? pidx(n, w.i, w.j, w.k) : 0;
+      w.next();
+      vr[k] = in ? gr[i] : (T)0;
+      vu[k] = in ? gu[i] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = base + threadIdx.x + k * NT;
+      if (i < cnt) {
+        lr[i] = vr[k];
+        lu[li[k]] = vu[k];
+      }
+    }
+  }
+}
+
 // f of level l - 1 = R f of level l (mean of the 8 children, summed in FP64
 // in the order of the global restriction kernel); both plain, in LDS
 template <class T>
@@ -398,8 +427,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   if (g.mode == 0) {  // f of the top level; the coarser ones are restricted here
     blk_copy<T, true, false>(sm + o.f[g.top], const_cast<T*>(g.f[g.top]), g.n[g.top]);
   } else {
-    blk_copy<T, true, false>(sm + o.rt, const_cast<T*>(g.rt), g.n[g.top]);
-    blk_copy<T, true, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);
+    blk_load_rhs_u(sm + o.rt, g.rt, sm + o.u[g.top], g.u[g.top], g.n[g.top]);
   }
   __syncthreads();
   if (g.mode == 0)

@@ -65,7 +65,8 @@ struct SmoothArgs {
   // caller's FP64 solution) -- written (1) or added (2) -- instead of u
   double* out;
   int outmode;
-  // residual-restriction epilogue (RES kernels, in place only): uc = R u and
+  // residual-restriction epilogue (RES kernels; k_smooth_z: in place only,
+  // k_smooth_cols: two copies on global levels, rmode 0): uc = R u and
   // rc = R (rhs - L u) on the coarse target -- rmode 0: C / 2 of the segment
   // (coarse segment storage); 1: the genuine coarse cells (global level)
   int rmode;
@@ -101,9 +102,7 @@ k_smooth_z(SmoothArgs<T> a) {
   const Box B = seg_box(gu, q);
   const int n = gu.n;
   const bool inpl = a.inplace != 0;
-  // tile halo: NS columns; a residual over two copies needs the neighbours of
-  // the output columns final too, one more
-  const int H = NS + (RES && !inpl ? 1 : 0);
+  constexpr int H = NS;  // tile halo
   const int txw = a.txw, tyw = a.tyw, sx = txw - 2 * H, sy = tyw - 2 * H;
   // blocks are dealt round-robin to the L2 domains: give each domain a
   // contiguous range of tiles so neighbouring tiles share an L2
@@ -144,9 +143,7 @@ k_smooth_z(SmoothArgs<T> a) {
   // The epilogue trails the last plane by two steps (residual, then the
   // coarse cells of the last coarse plane).
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
-  // (over two copies the march starts one plane lower, so that the plane
-  // below the chunk is final for its residual too)
-  const int p0 = oz - NS - (RES && !inpl ? 1 : 0), p1 = zs1 - 1 + NS + 2 * RES;
+  const int p0 = oz - NS, p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box(a.gr, q);
