@@ -171,6 +171,9 @@ template <class T>
 struct Hier {
   std::vector<Geo> geo;          // storage geometry of u, t, rhs on each level
   std::vector<T*> u, t, rhs, f;  // f[l]: global right-hand-side hierarchy
+  // the FAS right-hand side a column-smoother pass forms on a small global
+  // level (a separate array: the pass's overlapping tiles still read rhs)
+  std::vector<T*> rf;
   // The temporally blocked smoother reads one copy of u and writes the other
   // (tiles overlap by their halo, so an in-place update would race); u[l] is
   // the current copy, ua[l] / ub[l] the pair.
@@ -264,6 +267,14 @@ static void* dalloc(fmg_plan* P, size_t bytes) {
 
 static long long cube(long long x) { return x * x * x; }
 
+// Two-copy passes on levels of edge up to kLatencyEdge are chains of memory
+// round trips rather than streams.  On global levels they run in the column
+// smoother, which loads a whole z chunk at once; on segment levels (reached
+// only with the box and in-place smoothers off) the z march takes one column
+// per thread and keeps two planes in flight, so a step's loads have two steps
+// to arrive (four in flight were slower)
+constexpr int kLatencyEdge = 64;
+
 template <class T>
 static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
   int L = P->L;
@@ -273,6 +284,7 @@ static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
   H.ub.assign(L, nullptr);
   H.t.assign(L, nullptr);
   H.rhs.assign(L, nullptr);
+  H.rf.assign(L, nullptr);
   H.f.assign(L, nullptr);
   for (int l = 0; l < L; ++l) {
     int n = P->N >> (L - 1 - l);
@@ -287,6 +299,7 @@ static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
     if (l < L - 1) {
       H.t[l] = (T*)dalloc(P, sizeof(T) * cnt);
       H.rhs[l] = (T*)dalloc(P, sizeof(T) * cnt);
+      if (!sr && n <= kLatencyEdge) H.rf[l] = (T*)dalloc(P, sizeof(T) * cnt);
     }
   }
 }
@@ -306,13 +319,6 @@ static dim3 grid_for(long long cells, int nseg) {
 template <int NS>
 constexpr int kPrefetch = 1;
 
-// Two-copy passes on levels of edge up to kLatencyEdge are chains of memory
-// round trips rather than streams.  On global levels they run in the column
-// smoother, which loads a whole z chunk at once; on segment levels (reached
-// only with the box and in-place smoothers off) the z march takes one column
-// per thread and keeps two planes in flight, so a step's loads have two steps
-// to arrive (four in flight were slower)
-constexpr int kLatencyEdge = 64;
 
 template <class X>
 static bool nonnull(const X&) { return true; }
@@ -569,9 +575,10 @@ struct Exec {
 
   // NS half-sweeps with prologue PRO on a small global level, one column
   // per thread with its whole z chunk in registers (two copies); RES: the
-  // pass also restricts u and the residual to level l - 1
+  // pass also restricts u and the residual to level l - 1; fas: it first
+  // forms the FAS right-hand side rhs + L u and t = u of this level
   template <int NS, int PRO, int RES>
-  void smooth_cols(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc) {
+  void smooth_cols(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, int fas = 0) {
     constexpr int NT = 1024, ZC = 2, HH = NS + RES;
     const Geo& G = H.geo[l];
     const int n = G.n;
@@ -579,6 +586,8 @@ struct Exec {
       throw hip_error("internal: the column smoother takes global levels");
     if (PRO != PRO_LOAD && (!c || (PRO == PRO_CORRECT && !ct)))
       throw hip_error("internal: null coarse increment");
+    if (fas && (PRO != PRO_LOAD || !H.t[l] || !H.rf[l]))
+      throw hip_error("internal: FAS prologue without a load pass, t or its rhs array");
     SmoothArgs<T> a{};
     a.uin = H.u[l];
     a.u = H.u[l] == H.ua[l] ? H.ub[l] : H.ua[l];
@@ -594,6 +603,9 @@ struct Exec {
     a.uc = RES ? H.u[l - 1] : nullptr;
     a.rc = RES ? H.rhs[l - 1] : nullptr;
     a.gcr = H.geo[l > 0 ? l - 1 : 0];
+    a.fas = fas;
+    a.rhsw = fas ? H.rf[l] : nullptr;
+    a.tw = fas ? H.t[l] : nullptr;
     const double h = 1.0 / (double)n;
     a.h2 = (T)(h * h);
     // tile shape: the fewest loaded columns covering the level; even extents,
@@ -624,25 +636,41 @@ struct Exec {
     double rd = PRO == PRO_CORRECT ? 1.25 : PRO == PRO_INTERP ? 0.125 : 1.0;
     double bytes = sizeof(T) * (2.0 + rd) * c_cells(G);
     if (RES) bytes += 2.0 * sizeof(T) * c_cells(G) / 8.0;
+    if (fas) bytes += 2.0 * sizeof(T) * c_cells(G);  // rhs and t written
     run(clabel<NS, PRO, RES>(), bytes, dim3(per * a.nxcd), dim3(NT),
         k_smooth_cols<T, NS, PRO, RES, ZC>, a);
   }
 
   template <int PRO>
   void smooth_z_ns(int ns, bool inpl, int l, const T* rhs, Geo gr, const T* c, const T* ct,
-                   Geo gc, double* out = nullptr, int outmode = 0) {
+                   Geo gc, double* out = nullptr, int outmode = 0, int fas = 0) {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if (!inpl && !H.geo[l].ghost && H.geo[l].n <= kLatencyEdge) {
-      if (ns == 2) smooth_cols<2, PRO, 0>(l, rhs, gr, c, ct, gc);
-      else smooth_cols<4, PRO, 0>(l, rhs, gr, c, ct, gc);
+    if (fas && !cols_level(l)) throw hip_error("internal: FAS prologue off the column smoother");
+    if (cols_level(l) && !inpl) {
+      if (ns == 2) smooth_cols<2, PRO, 0>(l, rhs, gr, c, ct, gc, fas);
+      else smooth_cols<4, PRO, 0>(l, rhs, gr, c, ct, gc, fas);
     } else if (!inpl && H.geo[l].n <= kLatencyEdge) {
       if (ns == 2) smooth_z<2, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
       else smooth_z<4, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
     } else if (ns == 2 && !inpl) smooth_z<2, RY2, PRO>(l, rhs, gr, c, ct, gc, false);
     else if (ns == 2) smooth_z<2, 2, PRO>(l, rhs, gr, c, ct, gc, true, out, outmode);
     else smooth_z<4, 2, PRO>(l, rhs, gr, c, ct, gc, inpl, out, outmode);
+  }
+
+  // is level l a small global level, whose fused passes run in the column
+  // smoother?
+  bool cols_level(int l) const {
+    const Geo& G = H.geo[l];
+    return !G.ghost && nseg(l) == 1 && G.n <= kLatencyEdge;
+  }
+
+  // can the first pre-smoothing pass of level l form its FAS right-hand side
+  // (the column smoother's prologue), so that the restriction into it need
+  // not?
+  bool pass_fas(int l) const {
+    return l > P->Lc && P->fused && P->nu1 > 0 && cols_level(l);
   }
 
   // can level l's segments be smoothed in place, one workgroup each, with
@@ -760,7 +788,8 @@ struct Exec {
       smooth_box(l, rhs, gr, nu, pro, d, dt, Gc, fas, rmode);
       return rmode >= 0 && pro != PRO_CORRECT;
     }
-    if (fas) throw hip_error("internal: FAS prologue requested off the box path");
+    if (fas && (pro != PRO_LOAD || !pass_fas(l)))
+      throw hip_error("internal: FAS prologue requested off the box and column smoothers");
     if (st == 0 || !P->fused) {
       if (pro == PRO_CORRECT)
         run("k_correct", sizeof(T) * 2.25 * st_cells(G), grid_for(cube(G.m), nseg(l)),
@@ -786,18 +815,23 @@ struct Exec {
         // the last pass of a pre-smoothing also restricts (residual epilogue)
         smooth_z<2, 2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, true, nullptr, 0, rmode);
         restricted = true;
-      } else if (pr == PRO_LOAD && rmode == 0 && !inpl && !G.ghost && st == ns &&
-                 G.n <= kLatencyEdge) {
+      } else if (pr == PRO_LOAD && rmode == 0 && !inpl && cols_level(l) && st == ns) {
         // ... and over two copies on the small global levels
-        if (ns == 2) smooth_cols<2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc);
-        else smooth_cols<4, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc);
+        const int pf = first ? fas : 0;
+        if (ns == 2) smooth_cols<2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, pf);
+        else smooth_cols<4, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, pf);
         restricted = true;
       } else if (pr == PRO_CORRECT) {
         smooth_z_ns<PRO_CORRECT>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       } else if (pr == PRO_INTERP) {
         smooth_z_ns<PRO_INTERP>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
       } else {
-        smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om);
+        smooth_z_ns<PRO_LOAD>(ns, inpl, l, rhs, gr, d, dt, Gc, out, om, first ? fas : 0);
+      }
+      // a FAS prologue over two copies put the right-hand side in rf
+      if (first && fas && !boxp) {
+        rhs = H.rf[l];
+        gr = G;
       }
       st -= ns;
       first = false;
@@ -921,18 +955,21 @@ struct Exec {
   // FAS V-cycle on global level l with right-hand side rhs (Fig. 1)
   // presmoothed: S^nu1 has already been applied (fused with the FMG step),
   // and restricted tells whether that pass also restricted
-  // fas: rhs holds the restricted residual only, the coarse kernel forms the
-  // FAS right-hand side (levels up to Lc)
+  // fas: rhs holds the restricted residual only; the coarse kernel (levels up
+  // to Lc) or the first pre-smoothing pass (column smoother) forms the FAS
+  // right-hand side
   void vcycle_global(int l, const T* rhs, bool presmoothed = false, bool fas = false,
                      bool restricted = false) {
     if (l <= P->Lc) {
       coarse(l, 1, rhs, fas ? 1 : 0);
       return;
     }
-    if (fas) throw hip_error("internal: deferred FAS right-hand side above the coarse levels");
+    if (fas && (presmoothed || !pass_fas(l)))
+      throw hip_error("internal: deferred FAS right-hand side without a pass to form it");
     const Geo& G = H.geo[l];
-    if (!presmoothed) restricted = smooth(l, rhs, G, P->nu1, PRO_LOAD, 0, 0);
-    const bool cf = l - 1 <= P->Lc;
+    if (!presmoothed) restricted = smooth(l, rhs, G, P->nu1, PRO_LOAD, fas ? 1 : 0, 0);
+    if (fas) rhs = H.rf[l];  // the pre-smoothing formed the FAS right-hand side there
+    const bool cf = l - 1 <= P->Lc || pass_fas(l - 1);
     descend(l, rhs, G, 0, 1, restricted, cf);
     vcycle_global(l - 1, H.rhs[l - 1], false, cf);
     smooth(l, rhs, G, P->nu2, PRO_CORRECT);
@@ -955,7 +992,7 @@ struct Exec {
       descend(l, rhs, gr, 0, 0, restricted, next_fas);
       vcycle_sr(l - 1, top, false, false, next_fas);
     } else {
-      const bool cf = l - 1 <= P->Lc;
+      const bool cf = l - 1 <= P->Lc || pass_fas(l - 1);
       descend(l, rhs, gr, 1, 1, restricted, cf);  // owner-computes transition restriction
       vcycle_global(l - 1, H.rhs[l - 1], false, cf);
     }

@@ -26,7 +26,10 @@
 //    march, and u goes to the other copy;
 //  * with RES, the pass also forms uc = R u and rc = R (rhs - L u) on the
 //    coarse level (Eqs. 3-4): the halo is one cell wider, so the neighbours of
-//    the output cells are final too.
+//    the output cells are final too;
+//  * with the FAS flag (load prologue), the pass first forms the FAS
+//    right-hand side R res + L u of the level just restricted into (Eq. 4)
+//    from the loaded chunk, and stores it and t = u on its output cells.
 //
 // Global levels only (no segments): the tile covers the domain, out-of-domain
 // neighbours are the zeros of the Dirichlet boundary.
@@ -186,6 +189,32 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < Z; ++j) ex[j][t] = U[j];
   __syncthreads();
+
+  if (PRO == PRO_LOAD && a.fas) {
+    // rhs = R res + L u (FP64, neighbours summed in the order of the
+    // single-cell kernels; out-of-domain neighbours are the zeros loaded)
+    const double s2 = (double)n * (double)n;
+#pragma unroll
+    for (int j = 1; j < Z - 1; ++j) {
+      const int z = z0 + j;
+      const T* pl = ex[j];
+      double sn = (double)pl[xn];
+      sn += (double)pl[xn + 1];
+      sn += (double)pl[yn];
+      sn += (double)pl[yp];
+      sn += (double)U[j - 1];
+      sn += (double)U[j + 1];
+      const double nb = (double)(6 + nbxy + (z == 0) + (z == n - 1));
+      const double Lu = (sn - nb * (double)U[j]) * s2;
+      const bool v = act && z >= 0 && z < n;
+      F[j] = v ? (T)((double)F[j] + Lu) : F[j];
+      if (v && outc && j >= HZ && j < HZ + ZC) {
+        a.rhsw[pr + z * mr] = F[j];
+        a.tw[pu + z * mu] = U[j];
+      }
+    }
+    __syncthreads();  // the loaded values were read before the first half-sweep writes
+  }
 
   // half-sweep s updates colour (s - 1) & 1, red ((x + y + z) even) first.
   // Of planes 2k and 2k + 1 the column's cell of that colour is plane

@@ -73,6 +73,12 @@ struct SmoothArgs {
   T* uc;
   T* rc;
   Geo gcr;
+  // FAS prologue (k_smooth_cols, load prologue): rhs holds R res of the level
+  // above; the pass forms rhs = R res + L u (Eq. 4) and uses it, and stores
+  // it over rhs (rhsw) and t = u (tw) on its output cells
+  int fas;
+  T* rhsw;
+  T* tw;
 };
 
 template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
