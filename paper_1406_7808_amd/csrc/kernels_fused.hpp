@@ -654,6 +654,26 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   const T* __restrict__ rb = a.rhs + Br.base;
   const bool fas = PRO == PRO_LOAD && a.fas > 0;
 
+  // the load prologue copies the box straight into LDS (global_load_lds, 16
+  // bytes per lane, 1 KiB per wavefront instruction, no registers), issued
+  // first so that the slot setup overlaps it; cells outside the domain are
+  // zeroed once it has landed.  Needs 16-byte alignment of the box and its
+  // length.
+  const long long bytes = (long long)mc * sizeof(T);
+  const bool dma = PRO == PRO_LOAD && ((B.base * (long long)sizeof(T)) & 15) == 0 && (bytes & 15) == 0;
+  if (dma) {
+    const int nw = NT >> 6, wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const char* src = reinterpret_cast<const char*>(ub);
+    char* dst = reinterpret_cast<char*>(bu);
+    for (long long ch = wv; ch * 1024 < bytes; ch += nw) {
+      const long long off = ch * 1024 + ln * 16;
+      if (off < bytes)
+        __builtin_amdgcn_global_load_lds(src + off,
+                                         (__attribute__((address_space(3))) void*)(dst + ch * 1024),
+                                         16, 0, 0);
+    }
+  }
+
   // cell pairs of C: pair (xp, y, z) holds x = a0 + 2 xp and x + 1; the
   // right-hand side and diagonal inverse of both cells stay in registers.
   // Set up first, so that the right-hand side loads overlap the box loads.
@@ -704,8 +724,26 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   // load of a batch in flight together (lanes outside the domain read element
   // 0 and store 0)
   constexpr int LB = PRO == PRO_LOAD ? kBoxLoads : kBoxLoadsCorrect;
+  if (dma) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the copy has landed in LDS
+    __syncthreads();
+    // zero the box's slabs outside the domain (boundary segments)
+    for (int d = 0; d < 3; ++d) {
+      const int wl = B.o[d] < 0 ? -B.o[d] : 0, wh = B.o[d] + m > n ? B.o[d] + m - n : 0;
+      for (int side = 0; side < 2; ++side) {
+        const int w = side ? wh : wl, s0 = side ? m - wh : 0;
+        const int cnt = w * m2;
+        for (int c = threadIdx.x; c < cnt; c += NT) {
+          const int k = s0 + c / m2, r = c - (c / m2) * m2, i = r % m, j = r / m;
+          // k runs along dimension d, (i, j) over the other two
+          const int l = d == 0 ? (j * m + i) * m + k : d == 1 ? (j * m + k) * m + i : (k * m + j) * m + i;
+          bu[l] = (T)0;
+        }
+      }
+    }
+  }
   Walk3 wl(threadIdx.x, NT, m, m);
-  for (int base = 0; base < mc; base += LB * NT) {
+  for (int base = dma ? mc : 0; base < mc; base += LB * NT) {
     T vu[LB], vd[LB], vt[LB];
     unsigned vin = 0;
 #pragma unroll
