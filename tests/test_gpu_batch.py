@@ -89,6 +89,20 @@ def test_batch_rejects_bad_problem():
     assert e.value.status == fmg.FMG_EINVAL and "problem 1" in str(e.value)
 
 
+@pytest.mark.parametrize("ms", [2, 4])
+def test_transition_into_a_column_level(ms):
+    """SR whose transition level (32^3, global) runs in the column smoother:
+    its first pre-smoothing pass forms the FAS right-hand side and t, and with
+    max_stages=2 a second pass restricts."""
+    print("transition", ms, flush=True)
+    N, L, K, S, J = 128, 7, 2, 4, [2, 4]
+    f = W.random_field(N, 1400 + ms)
+    plan = fmg.Plan(N, L, sr_levels=K, segments=S, buffers=J)
+    plan.set_tuning(max_stages=ms)
+    assert _rel(plan.execute(_gpu(f)), oracle.srfmg(f, L, K, S, J)) <= TOL
+    plan.close()
+
+
 @pytest.mark.parametrize("kw", [dict(max_stages=2), dict(seg_inplace=0), dict(box=0),
                                 dict(target_blocks=256), dict(max_stages=4, seg_inplace=0, box=0),
                                 dict(max_stages=2, seg_inplace=0, box=0)])
