@@ -73,8 +73,13 @@ __device__ inline T inv_diag(int nb) {
   return r;
 }
 
-// one cell of each colour: the i-th cell of colour 0 in (x fastest) order and
-// its x-neighbour, which is the i-th cell of colour 1 (n is even)
+// one cell of each colour: the i-th cell of colour 0 and its x-neighbour,
+// which is the i-th cell of colour 1 (n is even).  Cells are numbered x
+// fastest within pairs of rows (y, y + 1), alternating between the two rows:
+// a row's cells of one colour lie two apart, and the checkerboard shifts
+// them by one between the rows, so alternating lanes fall on the other half
+// of the LDS banks (two rows apart by 2(n + 2) + -2 words, 2 mod 4) and a
+// wavefront's 64-bit reads use every bank equally.
 template <class T>
 struct GsCell {
   int p, c, d;  // padded and plain index of the colour-0 cell; colour-1 offset
@@ -94,7 +99,8 @@ __device__ inline GsCell<T> gs_cell(int i, int n, int half) {
   g.inv0 = g.inv1 = (T)0;
   if (g.v) {
     const int hx = n >> 1;
-    const int row = i / hx, xh = i - row * hx;
+    const int rp = i / (2 * hx), w = i - rp * 2 * hx;  // pair of rows, place in it
+    const int row = 2 * rp + (w & 1), xh = w >> 1;
     const int z = row / n, y = row - z * n;
     const int q = (y + z) & 1;
     const int x0 = 2 * xh + q, x1 = 2 * xh + 1 - q;
