@@ -869,13 +869,19 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   }
 
   // write back: the compute region, and the ghosts when the prologue changed them
-  Walk3 ww(threadIdx.x, NT, m, m);
-  for (int c = threadIdx.x; c < mc; c += NT, ww.next()) {
-    const int x = B.o[0] + ww.i, y = B.o[1] + ww.j, z = B.o[2] + ww.k;
-    if (!in_dom(n, x, y, z)) continue;
-    const bool inC = x >= B.a[0] && x < B.b[0] && y >= B.a[1] && y < B.b[1] && z >= B.a[2] &&
-                     z < B.b[2];
-    if (inC || PRO == PRO_CORRECT) ub[c] = bu[c];
+  if constexpr (PRO == PRO_CORRECT) {
+    Walk3 ww(threadIdx.x, NT, m, m);
+    for (int c = threadIdx.x; c < mc; c += NT, ww.next()) {
+      const int x = B.o[0] + ww.i, y = B.o[1] + ww.j, z = B.o[2] + ww.k;
+      if (in_dom(n, x, y, z)) ub[c] = bu[c];
+    }
+  } else {  // only C (inside the domain): walk C itself
+    const int cc = cx * cy * cz;
+    Walk3 ww(threadIdx.x, NT, cx, cy, cc);
+    for (int c = threadIdx.x; c < cc; c += NT, ww.next()) {
+      const int l = ((B.a[2] - B.o[2] + ww.k) * m + (B.a[1] - B.o[1] + ww.j)) * m + (B.a[0] - B.o[0] + ww.i);
+      ub[l] = bu[l];
+    }
   }
   if (!epi) return;
 
