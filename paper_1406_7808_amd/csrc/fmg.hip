@@ -1011,12 +1011,26 @@ struct Exec {
     int L = P->L;
     H.f[L - 1] = const_cast<T*>(ftop);
     for (int l = 0; l < L; ++l) H.u[l] = H.ua[l];
-    // f hierarchy down to the coarse-level kernel's top (it restricts further)
-    for (int l = L - 1; l > P->Lc; --l) {
-      int n = P->N >> (L - 1 - l);
+    // f hierarchy down to the coarse-level kernel's top (it restricts
+    // further): up to four levels per launch, reading each fine block once
+    for (int l = L - 1; l > P->Lc;) {
+      const int n = P->N >> (L - 1 - l);
       lvl = l;
-      run("k_restrict_global", sizeof(T) * 1.125 * cube(n), grid_for(cube(n / 2), 1),
-          dim3(kBlock), k_restrict_global<T, T>, (const T*)H.f[l], n, H.f[l - 1]);
+      int d = l - P->Lc < 4 ? l - P->Lc : 4;
+      while (d > 1 && n % (2 << d)) --d;
+      if (d > 1) {
+        double cells = 0;
+        for (int k = 0; k <= d; ++k) cells += (double)cube(n >> k);
+        run("k_restrict_chain", sizeof(T) * cells, dim3((unsigned)cube(n / (2 << d))), dim3(1024),
+            k_restrict_chain<T>, (const T*)H.f[l], n, d, H.f[l - 1], H.f[l - 2],
+            // (levels past depth are never written; any valid pointer)
+            d > 2 ? H.f[l - 3] : H.f[l - 1], d > 3 ? H.f[l - 4] : H.f[l - 1]);
+        l -= d;
+      } else {
+        run("k_restrict_global", sizeof(T) * 1.125 * cube(n), grid_for(cube(n / 2), 1),
+            dim3(kBlock), k_restrict_global<T, T>, (const T*)H.f[l], n, H.f[l - 1]);
+        --l;
+      }
     }
     fin_done = false;
     want_out = P->K > 0 ? out : nullptr;

@@ -214,6 +214,55 @@ __global__ void k_restrict_global(const Tf* __restrict__ fine, int n, Tc* __rest
   coarse[((long long)Z * nc + Y) * nc + X] = (Tc)(s / 8.0);
 }
 
+// the right-hand-side hierarchy several levels at once: a workgroup reads a
+// (2 << depth)^3 block of the fine level once and writes the matching blocks
+// of the next depth coarser levels (c0 the next, c3 the fourth), each a mean
+// of 8 children summed in the order of k_restrict_global, the intermediate
+// levels kept in LDS.  depth 1..4; n divisible by 2 << depth.
+template <class T>
+__global__ void __launch_bounds__(1024) k_restrict_chain(const T* __restrict__ fine, int n, int depth,
+                                                         T* c0, T* c1, T* c2, T* c3) {
+  __shared__ T la[16 * 16 * 16], lb[8 * 8 * 8];
+  const int E = 2 << depth, nb = n / E;
+  const int bx = blockIdx.x % nb, by = (blockIdx.x / nb) % nb, bz = blockIdx.x / (nb * nb);
+  int e = E >> 1, nl = n >> 1;  // block and level edge of the level being written
+  for (int c = threadIdx.x; c < e * e * e; c += blockDim.x) {
+    const int X = c % e, Y = (c / e) % e, Z = c / (e * e);
+    const long long gx = (long long)bx * E + 2 * X, gy = (long long)by * E + 2 * Y,
+                    gz = (long long)bz * E + 2 * Z;
+    double s = 0.0;
+    for (int k = 0; k < 2; ++k)
+      for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) s += (double)fine[((gz + k) * n + (gy + j)) * n + (gx + i)];
+    const T v = (T)(s / 8.0);
+    c0[((long long)(bz * e + Z) * nl + (by * e + Y)) * nl + (bx * e + X)] = v;
+    la[c] = v;
+  }
+  __syncthreads();
+  T* src = la;
+  T* dst = lb;
+  for (int d = 1; d < depth; ++d) {
+    const int ec = e >> 1, ncl = nl >> 1;
+    T* out = d == 1 ? c1 : d == 2 ? c2 : c3;
+    for (int c = threadIdx.x; c < ec * ec * ec; c += blockDim.x) {
+      const int X = c % ec, Y = (c / ec) % ec, Z = c / (ec * ec);
+      double s = 0.0;
+      for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+          for (int i = 0; i < 2; ++i) s += (double)src[((2 * Z + k) * e + (2 * Y + j)) * e + (2 * X + i)];
+      const T v = (T)(s / 8.0);
+      out[((long long)(bz * ec + Z) * ncl + (by * ec + Y)) * ncl + (bx * ec + X)] = v;
+      dst[c] = v;
+    }
+    __syncthreads();
+    T* tmp = src;
+    src = dst;
+    dst = tmp;
+    e = ec;
+    nl = ncl;
+  }
+}
+
 // coarsest level: u = A^-1 rhs with the FP64 inverse precomputed on the host
 template <class T>
 __global__ void k_coarse_solve(T* __restrict__ u, const T* __restrict__ rhs,
