@@ -85,13 +85,20 @@ typedef struct {
 
 typedef struct fmg_plan fmg_plan;
 
-/* Host-only validation of (N, *p); no device call.  FMG_OK or FMG_EINVAL. */
+/* Host-only validation of (N, *p); no device call.  FMG_OK or FMG_EINVAL.
+ * The rules: the level hierarchy of Sec. 2 (N = n0 * 2^(levels-1)), the
+ * segment and buffer-width conditions of Sec. 4 (Eq. 5: even widths; each at
+ * least half the next finer one, so that a compute region's coarse support
+ * lies in the coarser compute region), sweep counts of the F(alpha, nu1, nu2)
+ * cycle of Sec. 3.2. */
 int32_t fmg_check_params(int32_t N, const fmg_params *p);
 
 /* Validate, select `device`, allocate all device workspace and precompute the
- * coarsest-level inverse (in FP64 on the host).  On success *out owns the
- * workspace until fmg_plan_destroy.  FMG_EINVAL, FMG_ENOMEM or FMG_EHIP on
- * failure (then *out is NULL). */
+ * coarsest-level inverse (in FP64 on the host; the exact coarsest solve of
+ * Fig. 1 and Fig. 2).  The workspace holds the global levels of Sec. 3 and
+ * the segment-private boxes (compute region plus frozen ghosts) of Sec. 4.
+ * On success *out owns the workspace until fmg_plan_destroy.  FMG_EINVAL,
+ * FMG_ENOMEM or FMG_EHIP on failure (then *out is NULL). */
 int32_t fmg_plan_create(int32_t N, const fmg_params *p, int32_t device, fmg_plan **out);
 
 /* Enqueue one solve on `stream`: u <- FMG(f) (Fig. 2 for sr_levels == 0,
@@ -145,15 +152,20 @@ int32_t fmg_plan_checkpoints(fmg_plan *plan, double *const *out);
  * is updated in place.  *iters and *relres (host, may be NULL) receive the
  * cycle count and the final max|f - L u| / max|f|.  Global FP64 plans only
  * (sr_levels == 0): FMG_ENOTSUP otherwise.  Synchronizes `stream` once per
- * cycle (the stopping test) and allocates a small temporary device buffer.
- * FMG_EINVAL for null or overlapping f/u, rtol < 0 or maxit < 0. */
+ * cycle (the stopping test); rtol == 0 runs exactly maxit cycles and forms
+ * the residual once, after the last (nothing waits between cycles).  The
+ * norm partials live in the plan's workspace: the call allocates nothing.
+ * FMG_EINVAL for null or overlapping f/u, rtol < 0, maxit < 0, or a residual
+ * that is not finite (NaN or Inf in f or u). */
 int32_t fmg_plan_vcycles(fmg_plan *plan, const double *f, double *u, double rtol, int32_t maxit,
                          int32_t *iters, double *relres, void *stream);
 
 /* Free the workspace (synchronizes the plan's device).  NULL is accepted. */
 int32_t fmg_plan_destroy(fmg_plan *plan);
 
-/* create + execute + stream synchronize + destroy. */
+/* create + execute + stream synchronize + destroy: one solve of Fig. 2
+ * (sr_levels == 0) or Fig. 5, with the arguments, layout and errors of
+ * fmg_plan_create and fmg_plan_execute; allocates and frees the workspace. */
 int32_t fmg_solve(const double *f, int32_t N, const fmg_params *p, double *u, void *stream);
 
 /* Device bytes held by the plan. */
@@ -211,6 +223,7 @@ int32_t fmg_schedule_model(int32_t N, const fmg_params *p, fmg_schedule_stat *ou
 int32_t fmg_residual_norms(const double *f, const double *u, int32_t N, double *out,
                            void *stream);
 int32_t fmg_diff_norms(const double *u, const double *v, int32_t N, double *out, void *stream);
+
 
 /*
  * Batches of independent solves (sizes, parameters and tunings may differ).

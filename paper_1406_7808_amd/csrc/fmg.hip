@@ -236,6 +236,7 @@ struct fmg_plan {
   double* ws_finest = nullptr;  // second copy of the finest global FP64 level
   bool finest_odd = false;      // the finest level ends in its second copy
   float* r32 = nullptr;  // FP32 right-hand side of the inner solves
+  double* vpart = nullptr;  // norm partials of the V-cycle iteration (global FP64 plans)
   Prof prof;
   bool virt = false;              // workspace is virtual (schedule model only)
   uintptr_t virt_next = 1 << 20;  // next virtual address
@@ -1182,7 +1183,10 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
     P->Ainv = (double*)dalloc(P, sizeof(double) * inv.size());
     if (P->precision == FMG_FP64) {
       build_hier(P, P->h64, true);
-      if (P->K == 0) P->ws_finest = P->h64.ub[P->L - 1];
+      if (P->K == 0) {
+        P->ws_finest = P->h64.ub[P->L - 1];
+        P->vpart = (double*)dalloc(P, sizeof(double) * (size_t)(2 * kNormMaxBlocks + 4));
+      }
       settle_schedule(P);
     } else {
       build_hier(P, P->h32, false);
@@ -1405,6 +1409,7 @@ int32_t fmg_plan_vcycles(fmg_plan* P, const double* f, double* u, double rtol, i
   try {
     hipcheck(hipSetDevice(P->device), "hipSetDevice");
     int it = vcycle_solve(P, f, u, rtol, maxit, relres, (hipStream_t)stream);
+    if (it < 0) return fail(FMG_EINVAL, "the residual is not finite (NaN or Inf in f or u)");
     if (iters) *iters = it;
   } catch (const hip_error& ex) {
     return fail(FMG_EHIP, ex.what());
@@ -1488,7 +1493,7 @@ int32_t fmg_plan_profile_read(fmg_plan* P, fmg_kernel_stat* out, int32_t cap, in
 // res[0..1] (device), with nb partial pairs in part (device)
 static long long norm_blocks(int n) {
   long long nb = (cube(n) + kNormThreads - 1) / kNormThreads;
-  return nb > 1024 ? 1024 : nb;
+  return nb > kNormMaxBlocks ? kNormMaxBlocks : nb;
 }
 
 static hipError_t norms_launch(const double* a, const double* b, int n, int mode, double* part,
@@ -1528,7 +1533,10 @@ static int32_t norms(const double* a, const double* b, int32_t n, int mode, doub
 
 // f4: V(nu1, nu2) cycles on the global hierarchy from the guess in u until
 // max|f - L u| <= rtol max|f| or maxit cycles (the stopping rule of the
-// oracle's iterated V-cycles); returns the cycle count
+// oracle's iterated V-cycles); returns the cycle count, or -1 when the
+// residual is not finite (NaN or Inf in f or u).  rtol == 0 runs exactly
+// maxit cycles and forms the residual once, after the last, so that nothing
+// waits on the host between cycles.  The norms' partials live in the plan.
 static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, int maxit,
                         double* relres, hipStream_t s) {
   const int N = P->N, L = P->L;
@@ -1538,25 +1546,28 @@ static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, in
   H.ub[L - 1] = P->ws_finest;
   for (int l = 0; l < L; ++l) H.u[l] = H.ua[l];
   H.f[L - 1] = const_cast<double*>(f);
+  if (!P->vpart) throw hip_error("internal: plan holds no norm partials");
   const long long nb = norm_blocks(N);
-  double* part = nullptr;
-  hipcheck(hipMalloc(&part, sizeof(double) * (size_t)(2 * nb + 4)), "hipMalloc");
-  struct Free {
-    double* p;
-    ~Free() { (void)hipFree(p); }
-  } guard{part};
+  double* part = P->vpart;
   double* res = part + 2 * nb;
   double h[4];
   hipcheck(norms_launch(f, f, N, 2, part, res + 2, s), "norms");
   int it = 0;
   double rn = 0.0, fn = 0.0;
+  const bool fixed = rtol == 0.0;
   for (;;) {
+    if (fixed && it < maxit) {
+      E.vcycle_global(L - 1, f);
+      ++it;
+      continue;
+    }
     hipcheck(norms_launch(f, H.u[L - 1], N, 0, part, res, s), "norms");
     hipcheck(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
     rn = h[0];
     fn = h[2];
-    if (rn <= rtol * fn || it >= maxit) break;
+    if (!std::isfinite(rn) || !std::isfinite(fn)) return -1;
+    if (fixed || rn <= rtol * fn || it >= maxit) break;
     E.vcycle_global(L - 1, f);
     ++it;
   }

@@ -17,12 +17,17 @@
 namespace fmg {
 
 constexpr int kNormThreads = 256;
+constexpr int kNormMaxBlocks = 1024;  // partial pairs of one reduction, at most
+
+// the larger of a and b, and NaN when either is NaN (a NaN residual must not
+// read as a zero norm)
+__device__ inline double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
 
 __device__ inline void wave_reduce(double& mx, double& ss) {
   for (int off = 32; off > 0; off >>= 1) {
     const double om = __shfl_xor(mx, off, 64);
     const double os = __shfl_xor(ss, off, 64);
-    mx = om > mx ? om : mx;
+    mx = max_nan(om, mx);
     ss += os;
   }
 }
@@ -39,7 +44,7 @@ __device__ inline void block_reduce(double& mx, double& ss) {
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-      mx = smx[i] > mx ? smx[i] : mx;
+      mx = max_nan(smx[i], mx);
       ss += sss[i];
     }
   }
@@ -61,8 +66,7 @@ __global__ void __launch_bounds__(kNormThreads) k_norms(const double* __restrict
     } else {
       r = mode == 1 ? f[c] - u[c] : f[c];
     }
-    const double a = r < 0 ? -r : r;
-    mx = a > mx ? a : mx;
+    mx = max_nan(fabs(r), mx);
     ss += r * r;
   }
   block_reduce(mx, ss);
@@ -78,7 +82,7 @@ __global__ void __launch_bounds__(kNormThreads) k_norms_final(const double* __re
                                                               double* __restrict__ out) {
   double mx = 0.0, ss = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    mx = part[2 * i] > mx ? part[2 * i] : mx;
+    mx = max_nan(part[2 * i], mx);
     ss += part[2 * i + 1];
   }
   block_reduce(mx, ss);

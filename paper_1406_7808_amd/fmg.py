@@ -234,7 +234,8 @@ class Plan:
     def vcycles(self, f, u, rtol=1e-4, maxit=50, stream=None):
         """V(nu1, nu2) cycles from the guess in u (updated in place) until
         max|f - L u| <= rtol max|f| or maxit cycles; returns (cycles, relres).
-        Global FP64 plans only.  Synchronizes the stream once per cycle."""
+        Global FP64 plans only.  Synchronizes the stream once per cycle;
+        rtol=0 runs exactly maxit cycles with one residual check at the end."""
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
         _check(lib().fmg_plan_vcycles(self._h, _dev(f, self.N), _dev(u, self.N), float(rtol),

@@ -110,6 +110,33 @@ def test_global_fmg_sweep_counts(sweeps):
     assert _rel(u, oracle.fmg(f, L, alpha=sweeps[2], nu1=sweeps[0], nu2=sweeps[1])) <= TOL
 
 
+# Sweep counts other than F(1,2,2) take other kernel paths: an FMG stage of
+# two half-sweeps interpolates in a separate launch before a pass that also
+# restricts; a last pre-smoothing pass of two half-sweeps carries the residual
+# epilogue, of four it does not; nu = 0 runs the separate correction launch or
+# no pre-smoothing pass at all; the box smoother takes other sweep counts.
+SWEEPS = [(1, 1, 0), (3, 1, 2), (0, 2, 1), (2, 2, 2), (2, 0, 1)]
+
+
+@pytest.mark.parametrize("sweeps", SWEEPS)
+def test_global_fmg_sweep_counts_128(sweeps):
+    N, L = 128, 7
+    _say("global sweeps 128", sweeps)
+    f = W.random_field(N, 70 + sum(sweeps))
+    u = fmg.solve(_gpu(f), L, sweeps=sweeps)
+    assert _rel(u, oracle.fmg(f, L, alpha=sweeps[2], nu1=sweeps[0], nu2=sweeps[1])) <= TOL
+
+
+@pytest.mark.parametrize("N,L,K,S,J", [(64, 6, 2, 2, [2, 2]), (128, 7, 3, 4, [2, 4, 6])])
+@pytest.mark.parametrize("sweeps", SWEEPS)
+def test_sr_fmg_sweep_counts(N, L, K, S, J, sweeps):
+    _say("sr sweeps", N, L, K, S, J, sweeps)
+    f = W.random_field(N, 80 + N + 3 * sweeps[0] + 5 * sweeps[1] + 7 * sweeps[2])
+    u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J, sweeps=sweeps)
+    ref = oracle.srfmg(f, L, K, S, J, alpha=sweeps[2], nu1=sweeps[0], nu2=sweeps[1])
+    assert _rel(u, ref) <= TOL
+
+
 # --- segmental refinement --------------------------------------------------------
 
 SR_CASES = [
@@ -174,6 +201,46 @@ def test_full_size_sr(fourier256):
     plan.close()
 
 
+def test_full_size_sr_sweep_counts(fourier256):
+    """The 256^3 SR workload with F(2,3,1) instead of F(1,2,2): the finest
+    level's passes split 4 + 4 + 2 (the last with the residual epilogue) and
+    the box levels run other sweep counts."""
+    f = fourier256[0]
+    sw = (3, 1, 2)
+    _say("full sr 256 sweeps", sw)
+    u = fmg.solve(_gpu(f), 8, sr_levels=3, segments=8, buffers=[2, 4, 6], sweeps=sw)
+    assert _rel(u, oracle.srfmg(f, 8, 3, 8, [2, 4, 6], alpha=sw[2], nu1=sw[0], nu2=sw[1])) <= TOL
+
+
+def test_full_size_sr_random_field():
+    """The 256^3 SR configuration on a rough (uniform random) right-hand side."""
+    _say("full sr 256 random")
+    f = W.random_field(256, 256256)
+    u = fmg.solve(_gpu(f), 8, sr_levels=3, segments=8, buffers=[2, 4, 6])
+    assert _rel(u, oracle.srfmg(f, 8, 3, 8, [2, 4, 6])) <= TOL
+
+
+@pytest.fixture(scope="module")
+def polynomial512():
+    return W.polynomial(512)
+
+
+def test_512_fp64_global(polynomial512):
+    """The 512^3 workload (8 levels, coarsest 4^3) in FP64, plain global FMG."""
+    f = polynomial512[0]
+    _say("512 fp64 global")
+    u = fmg.solve(_gpu(f), 8)
+    assert _rel(u, oracle.fmg(f, 8)) <= TOL
+
+
+def test_512_fp64_sr(polynomial512):
+    """The 512^3 workload in FP64 with SR on the 3 finest levels, 16^3 segments."""
+    f = polynomial512[0]
+    _say("512 fp64 sr")
+    u = fmg.solve(_gpu(f), 8, sr_levels=3, segments=16, buffers=[2, 4, 6])
+    assert _rel(u, oracle.srfmg(f, 8, 3, 16, [2, 4, 6])) <= TOL
+
+
 # --- V-cycle iteration (the comparison solver) ---------------------------------------
 
 @pytest.mark.parametrize("N,L", [(32, 5), (64, 6), (48, 5)])
@@ -203,6 +270,16 @@ def test_vcycles_to_tolerance():
     with pytest.raises(fmg.FMGError) as e:
         fmg.Plan(N, L, sr_levels=2, segments=2, buffers=[2, 2]).vcycles(_gpu(f), u)
     assert e.value.status == fmg.FMG_ENOTSUP
+    # rtol = 0: exactly that many cycles, one residual check at the end
+    u2 = torch.zeros_like(u)
+    it2, rr2 = plan.vcycles(_gpu(f), u2, rtol=0.0, maxit=it)
+    assert it2 == it and torch.equal(u, u2) and rr2 == rr
+    # a NaN in the guess is an error, not a converged solve
+    bad = torch.zeros_like(u)
+    bad[1, 2, 3] = float("nan")
+    with pytest.raises(fmg.FMGError) as e:
+        plan.vcycles(_gpu(f), bad, rtol=1e-4, maxit=5)
+    assert e.value.status == fmg.FMG_EINVAL
     plan.close()
 
 
