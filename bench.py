@@ -13,12 +13,19 @@ One step = one solve.  Three solvers are timed on the same right-hand side:
   global plain global FMG;
   sr32r  the same SR solve with FP32 multigrid and 2 FP64 residual
          corrections.
-`value` = N^3 / (time of one SR solve), inputs resident in HBM.
+`value` = N^3 / (time of one SR solve), inputs resident in HBM.  Each solver
+also reports its fraction of the HBM peak: algorithmic bytes per solve (the
+library's schedule model) and, where committed counter readings of the same
+kernel sources exist, measured HBM bytes per solve, each over its time.
 
-Also reported: the dominant kernel's roofline (HIP events around each of its
-launches in a profiled pass, algorithmic bytes from the launch geometry), the
-CPU oracle's throughput on a bounded sample, and the accuracy of each solver
-against the closed-form discrete solution.
+Also reported, outside the timed region: the same three solvers on the 32^3
+sine and 512^3 polynomial workloads; the V-cycle solver to a relative
+residual of 1e-4; error and residual of every solver for N = 32..256; the
+dominant kernel's roofline (HIP events around each of its launches, with the
+stream held by a sleep kernel until every launch is queued); the CPU
+oracle's throughput on a bounded sample (built for the host CPU, at all
+threads and at one); and the accuracy against the closed-form discrete
+solution.
 """
 import argparse
 import hashlib
@@ -27,6 +34,7 @@ import math
 import os
 import re
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +43,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 N, LEVELS, K, S, J = 256, 8, 3, 8, (2, 4, 6)
 METRIC = "FMG solve DOF/s + % HBM peak at 256^3 (global vs SR vs FP32-refined SR)"
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+# solver variants on an edge-N workload: keyword arguments of fmg.Plan
+def variant_specs(levels, sr_levels, segments, buffers):
+    return {
+        "sr": dict(levels=levels, sr_levels=sr_levels, segments=segments, buffers=buffers),
+        "global": dict(levels=levels),
+        "sr32r": dict(levels=levels, sr_levels=sr_levels, segments=segments, buffers=buffers,
+                      precision="fp32_refined", refine_iters=2),
+    }
+
+
+SPECS = variant_specs(LEVELS, K, S, J)
 
 
 def source_hash():
@@ -60,30 +81,31 @@ def symbol_pattern(label, dtype="double"):
                                                                           ry, res)
     if base == "k_smooth_box":
         return r"fmg::k_smooth_box<%s, %d>" % (dtype, pro[args[0]])
+    if base == "k_smooth_cols":
+        ns = int(args[1][2:])
+        res = 1 if "res" in args[2:] else 0
+        return r"fmg::k_smooth_cols<%s, %d, %d, %d, \d+>" % (dtype, ns, pro[args[0]], res)
     return r"fmg::%s[<(]" % base
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 counter
-    summaries (profiles/traffic.json), or None when absent or taken on
-    other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+def load_traffic():
+    """profiles/traffic.json if it was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC):
         return None
-    with open(path) as fh:
+    with open(TRAFFIC) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != source_hash() or t.get("symbol_pattern") != symbol_pattern(kernel):
+    if t.get("source_hash") != source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t
 
 
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
 
 
 def counter_pass(args):
-    """The workload run under rocprofv3 --pmc: a few headline solves, then a
-    plain device-to-device copy of COPY_BYTES whose counter readings scale
-    the solver's (FETCH_SIZE / WRITE_SIZE are reported in KiB)."""
+    """The workload run under rocprofv3 --pmc: `steps` solves of one variant,
+    then a plain device-to-device copy of COPY_BYTES whose counter readings
+    scale the solver's (FETCH_SIZE / WRITE_SIZE are reported in KiB)."""
     import torch
     from paper_1406_7808_amd import fmg
     from paper_1406_7808_amd import workloads as W
@@ -91,12 +113,13 @@ def counter_pass(args):
     torch.cuda.set_device(dev)
     f, _, _ = W.fourier(N)
     fd = torch.from_numpy(f).to(dev)
-    plan = fmg.Plan(N, LEVELS, sr_levels=K, segments=S, buffers=J)
+    spec = dict(SPECS[args.variant])
+    plan = fmg.Plan(N, spec.pop("levels"), **spec)
     u = torch.empty_like(fd)
     for _ in range(args.steps):
         plan.execute(fd, u)
     torch.cuda.synchronize()
-    print("counter pass: %d solves done" % args.steps, flush=True)
+    print("counter pass: %d %s solves done" % (args.steps, args.variant), flush=True)
     a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
     for _ in range(3):
@@ -113,13 +136,18 @@ def _pmc_rows(path):
         return list(csv.DictReader(fh))
 
 
-def traffic_from(fetch_csv, write_csv, kernel, out_path, commands):
-    """profiles/traffic.json from two rocprofv3 --pmc runs of counter_pass:
-    mean KiB per dispatch of `kernel`, scaled by the calibration copy's bytes
-    per KiB (the copy is the largest copyBuffer dispatch of the run), and the
-    same scaled figures for every kernel of the run."""
-    pat = re.compile(symbol_pattern(kernel))
-    res, table = {}, {}
+def _symbol(kernel_name):
+    return kernel_name.split("(")[0].replace("void ", "").strip()
+
+
+def traffic_from(variant, solves, fetch_csv, write_csv, commands):
+    """Add `variant` to profiles/traffic.json from two rocprofv3 --pmc runs
+    of counter_pass (`solves` solves each): per counter, every fmg:: dispatch
+    scaled by the calibration copy's bytes per counted unit (the copy is the
+    largest copyBuffer dispatch of the run); HBM bytes per solve, and per
+    kernel symbol the mean bytes per launch."""
+    res = {}
+    per_symbol = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = [r for r in _pmc_rows(path) if r.get("Counter_Name") == counter]
         copies = [r for r in rows if "copyBuffer" in r.get("Kernel_Name", "")]
@@ -128,36 +156,108 @@ def traffic_from(fetch_csv, write_csv, kernel, out_path, commands):
         big = max(int(r["Grid_Size"]) for r in copies)
         copy = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == big]
         scale = COPY_BYTES / (sum(copy) / len(copy))  # bytes per counted unit
-        kern = [float(r["Counter_Value"]) for r in rows if pat.search(r.get("Kernel_Name", ""))]
+        kern = [r for r in rows if "fmg::" in r.get("Kernel_Name", "")]
         if not kern:
-            raise SystemExit("traffic: no %s rows for %s in %s" % (counter, kernel, path))
-        res[counter] = {"dispatches": len(kern), "mean_counter": sum(kern) / len(kern),
-                        "copy_mean_counter": sum(copy) / len(copy),
+            raise SystemExit("traffic: no fmg:: dispatches in %s" % path)
+        total = sum(float(r["Counter_Value"]) for r in kern) * scale
+        res[counter] = {"dispatches": len(kern), "copy_mean_counter": sum(copy) / len(copy),
                         "copy_bytes": COPY_BYTES, "bytes_per_unit": scale,
-                        "bytes_per_launch": sum(kern) / len(kern) * scale}
-        for r in rows:
-            name = r.get("Kernel_Name", "").split("(")[0].replace("void ", "")
-            if "fmg::" not in name:
-                continue
-            key = "%s grid=%s" % (name, r["Grid_Size"])
-            e = table.setdefault(key, {"dispatches": 0})
-            e["dispatches"] = max(e["dispatches"], e.get("_n" + counter, 0) + 1)
-            e["_n" + counter] = e.get("_n" + counter, 0) + 1
-            e[counter + "_MB"] = e.get(counter + "_MB", 0.0) + float(r["Counter_Value"]) * scale / 1e6
-    for e in table.values():
-        n = e.pop("_nFETCH_SIZE", 1)
-        e["FETCH_SIZE_MB"] = round(e.get("FETCH_SIZE_MB", 0.0) / n, 2)
-        n = e.pop("_nWRITE_SIZE", 1)
-        e["WRITE_SIZE_MB"] = round(e.get("WRITE_SIZE_MB", 0.0) / n, 2)
-    out = {"kernel": kernel, "symbol_pattern": symbol_pattern(kernel),
-           "source_hash": source_hash(),
-           "bytes_per_launch": res["FETCH_SIZE"]["bytes_per_launch"]
-           + res["WRITE_SIZE"]["bytes_per_launch"],
-           "counters": res, "per_dispatch_MB": table, "commands": commands}
-    with open(out_path, "w") as fh:
-        json.dump(out, fh, indent=1)
-    print(json.dumps({k: v for k, v in out.items() if k != "per_dispatch_MB"}))
+                        "bytes_per_solve": total / solves}
+        for r in kern:
+            e = per_symbol.setdefault(_symbol(r["Kernel_Name"]), {})
+            c = e.setdefault(counter, [0, 0.0])
+            c[0] += 1
+            c[1] += float(r["Counter_Value"]) * scale
+    kernels = {}
+    for sym, e in per_symbol.items():
+        fe = e.get("FETCH_SIZE", [1, 0.0])
+        wr = e.get("WRITE_SIZE", [1, 0.0])
+        kernels[sym] = {"launches_per_solve": fe[0] / solves,
+                        "fetch_bytes_per_launch": fe[1] / fe[0],
+                        "write_bytes_per_launch": wr[1] / wr[0],
+                        "bytes_per_launch": fe[1] / fe[0] + wr[1] / wr[0]}
+    t = {}
+    if os.path.exists(TRAFFIC):
+        with open(TRAFFIC) as fh:
+            t = json.load(fh)
+    if t.get("source_hash") != source_hash() or "variants" not in t:
+        t = {"source_hash": source_hash(), "variants": {}}
+    t["variants"][variant] = {
+        "solves": solves,
+        "bytes_per_solve": res["FETCH_SIZE"]["bytes_per_solve"] + res["WRITE_SIZE"]["bytes_per_solve"],
+        "counters": res, "kernels": kernels, "commands": commands}
+    with open(TRAFFIC, "w") as fh:
+        json.dump(t, fh, indent=1, sort_keys=True)
+    print(json.dumps({"variant": variant, "bytes_per_solve": t["variants"][variant]["bytes_per_solve"]}))
     return 0
+
+
+def time_graph(run, steps, warmup):
+    """ms per call of run() (which enqueues on torch's current stream),
+    captured once into a graph and replayed `steps` times."""
+    import torch
+    for _ in range(max(1, warmup)):
+        run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    del graph
+    return e0.elapsed_time(e1) / steps
+
+
+def time_solver(fmg, fd, spec, steps, warmup, graph=True):
+    """(ms per solve, plan, u) for a plan of `spec` on fd."""
+    import torch
+    n = fd.shape[0]
+    sp = dict(spec)
+    plan = fmg.Plan(n, sp.pop("levels"), **sp)
+    u = torch.empty_like(fd)
+    if graph:
+        ms = time_graph(lambda: plan.execute(fd, u), steps, warmup)
+    else:
+        for _ in range(max(1, warmup)):
+            plan.execute(fd, u)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.execute(fd, u)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    return ms, plan, u
+
+
+def hbm_fracs(fmg, n, spec, ms, measured=None):
+    """Algorithmic bytes per solve (schedule model), measured bytes per solve
+    (if given) and their fractions of the HBM peak at ms per solve."""
+    sp = dict(spec)
+    _, model_bytes, _ = fmg.schedule_model(n, **sp)
+    out = {"model_bytes_per_solve": model_bytes,
+           "model_B_per_DOF": round(model_bytes / n ** 3, 2),
+           "model_GB_per_s": round(model_bytes / (ms * 1e-3) / 1e9, 1),
+           "hbm_frac_model": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "measured_bytes_per_solve": measured,
+           "hbm_frac_measured": (round(measured / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                 if measured else None)}
+    return out
 
 
 def batch_leg(precision, args):
@@ -168,8 +268,8 @@ def batch_leg(precision, args):
     from paper_1406_7808_amd import batched
     from paper_1406_7808_amd import workloads as W
     items = W.batch()
-    edges = [N for N, _, _ in items]
-    fs = [torch.from_numpy(W.fourier_field(N, k, a)).cuda() for N, k, a in items]
+    edges = [n for n, _, _ in items]
+    fs = [torch.from_numpy(W.fourier_field(n, k, a)).cuda() for n, k, a in items]
     us = [torch.empty_like(f) for f in fs]
     b, probs = batched.build(edges, precision=precision, streams=8, tuned=True, fs=fs, us=us)
     side = torch.cuda.Stream()
@@ -185,12 +285,191 @@ def batch_leg(precision, args):
     e1.record(side)
     side.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    dof = sum(N ** 3 for N in edges)
+    dof = sum(n ** 3 for n in edges)
     out = {"ms": round(ms, 4), "dof_per_s": dof / (ms * 1e-3), "solves": len(edges),
            "edges": {str(n): edges.count(n) for n in sorted(set(edges))}, "streams": 8,
            "graph": True, "workspace_MB": round(b.workspace_bytes / 2 ** 20, 1)}
     b.close()
     return out
+
+
+def dominant_kernel(fmg, plan, fd, traffic):
+    """Per-launch HIP events over 3 solves of the headline plan.  A sleep
+    kernel holds the stream first, so every launch and event is queued
+    before the GPU reaches them and each bracket holds only its kernel.  The
+    dominant kernel is the instantiation (one rocprofv3 symbol) with the
+    largest total time among those launched with more than one workgroup (a
+    single-workgroup kernel is latency bound and has no HBM roofline)."""
+    import torch
+    u = torch.empty_like(fd)
+    plan.execute(fd, u)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda._sleep(200_000_000)  # ~0.1 s of GPU cycles: the host queues ahead
+    for _ in range(3):
+        plan.execute(fd, u)
+    stats = plan.profile_read()
+    plan.profile(False)
+    by_kernel, label_of = {}, {}
+    for k, v in stats.items():
+        name = k.split("@")[0]
+        sym = symbol_pattern(name)
+        label_of.setdefault(sym, name)
+        a = by_kernel.setdefault(sym, [0, 0.0, 0.0])
+        for i in range(3):
+            a[i] += v[i]
+    single = ("k_coarse",)
+    cand = {s: v for s, v in by_kernel.items() if not label_of[s].startswith(single)}
+    sym = max(cand, key=lambda k: cand[k][1])
+    kern = label_of[sym]
+    launches, tot_ms, tot_bytes = cand[sym]
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    meas = None
+    if traffic and "sr" in traffic.get("variants", {}):
+        pat = re.compile(sym)
+        for s, e in traffic["variants"]["sr"]["kernels"].items():
+            if pat.fullmatch(s) or pat.match(s):
+                meas = e["bytes_per_launch"]
+    kernels = {k: {"launches": v[0] // 3, "ms_per_solve": round(v[1] / 3, 4),
+                   "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    roofline = {"bound": "hbm", "kernel": kern, "symbol": sym, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": meas, "launches_per_solve": launches // 3,
+                "avg_launch_us": round(tot_ms / launches * 1e3, 2),
+                "bytes_per_launch": tot_bytes / launches,
+                "event_sum_ms_per_solve": round(sum(v[1] for v in stats.values()) / 3, 4)}
+    return roofline, kernels
+
+
+def other_configs(fmg, W, ex, args):
+    """The 32^3 sine and 512^3 polynomial workloads: the three solvers each,
+    graph-replayed, with their HBM fractions and accuracy."""
+    import numpy as np
+    import torch
+    out = {}
+    cfgs = [("poisson3d-32^3-sine", 32, variant_specs(5, 2, 2, (2, 2))),
+            ("poisson3d-512^3-polynomial", 512, variant_specs(8, 3, 16, (2, 4, 6)))]
+    for name, n, specs in cfgs:
+        if n == 32:
+            f, uc = W.sine(n)
+            ud = uc * ex.sine_discrete(n)
+        else:
+            f, uc = W.polynomial(n)
+            ud = None  # the DST-II solve of 512^3 costs ~1 minute of host time: not here
+        fd = torch.from_numpy(f).cuda()
+        entry = {}
+        for v, spec in specs.items():
+            ms, plan, u = time_solver(fmg, fd, spec, args.steps, args.warmup)
+            e = {"ms": round(ms, 4), "dof_per_s": n ** 3 / (ms * 1e-3)}
+            e.update(hbm_fracs(fmg, n, spec, ms))
+            uh = u.cpu().numpy()
+            e["e_total"] = float(np.abs(uh - uc).max())
+            if ud is not None:
+                e["e_alg_over_e_disc"] = float(np.abs(uh - ud).max() / np.abs(ud - uc).max())
+            entry[v] = e
+            plan.close()
+            print("bench: %s %s %.3f ms/solve" % (name, v, ms), file=sys.stderr, flush=True)
+        out[name] = entry
+        del fd
+        torch.cuda.empty_cache()
+    return out
+
+
+def vcycle_leg(fmg, fd, ud, uc, edisc, args):
+    """The comparison solver (Sec. 7, Fig. 10) on the 256^3 workload: V(2,2)
+    cycles from u = 0 until max|f - L u| <= 1e-4 max|f|; then the same cycle
+    count timed as one graph (no residual checks inside)."""
+    import numpy as np
+    import torch
+    plan = fmg.Plan(N, LEVELS)
+    u = torch.zeros_like(fd)
+    it, rr = plan.vcycles(fd, u, rtol=1e-4, maxit=60)
+    uh = u.cpu().numpy()
+    w = torch.empty_like(fd)
+
+    def run():
+        w.zero_()
+        plan.vcycles(fd, w, rtol=0.0, maxit=it, residual=False)
+
+    ms = time_graph(run, max(3, args.steps // 4), 1)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(w, u))
+    out = {"rtol": 1e-4, "cycles": it, "relres_inf": rr, "ms": round(ms, 4),
+           "dof_per_s": N ** 3 / (ms * 1e-3), "graph_result_equals_iterated": same,
+           "e_alg_over_e_disc": float(np.abs(uh - ud).max() / edisc),
+           "e_total": float(np.abs(uh - uc).max())}
+    plan.close()
+    return out
+
+
+def convergence_study(fmg, W, ex):
+    """Error and residual (max norms) of G, SR and the V-cycle solver to
+    rtol 1e-4 for N = 32..256 on the Fourier right-hand side (Sec. 7,
+    Figs. 8 and 10): SR with 3 levels, 4^3 segments, buffers 2, 4, 6.  The
+    error is against the continuous solution at cell centers."""
+    import numpy as np
+    import torch
+    rows = {"N": [], "global": {"err": [], "res": []}, "sr": {"err": [], "res": []},
+            "vcycle": {"err": [], "res": [], "cycles": []}}
+    for n in (32, 64, 128, 256):
+        L = int(math.log2(n))
+        f, uc, _ = W.fourier(n)
+        fd = torch.from_numpy(f).cuda()
+        rows["N"].append(n)
+        for v, kw in (("global", {}), ("sr", dict(sr_levels=3, segments=4, buffers=(2, 4, 6)))):
+            u = fmg.solve(fd, L, **kw)
+            rows[v]["err"].append(float(np.abs(u.cpu().numpy() - uc).max()))
+            rows[v]["res"].append(fmg.residual_norms(fd, u)[0])
+        plan = fmg.Plan(n, L)
+        u = torch.zeros_like(fd)
+        it, _ = plan.vcycles(fd, u, rtol=1e-4, maxit=60)
+        plan.close()
+        rows["vcycle"]["err"].append(float(np.abs(u.cpu().numpy() - uc).max()))
+        rows["vcycle"]["res"].append(fmg.residual_norms(fd, u)[0])
+        rows["vcycle"]["cycles"].append(it)
+    for v in ("global", "sr", "vcycle"):
+        for q in ("err", "res"):
+            a = rows[v][q]
+            rows[v][q + "_order"] = [round(math.log2(a[i] / a[i + 1]), 3) for i in range(len(a) - 1)]
+    return rows
+
+
+def cpu_leg(f, fd_result):
+    """The oracle's SR solve of the 256^3 workload, built for this host's CPU
+    (-O3 -march=native), at all OpenMP threads for about 12 s and at one
+    thread for one solve."""
+    import numpy as np
+    import oracle
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    so = oracle.build_native(tempfile.mkdtemp(prefix="fmg_oracle_"))
+    oracle.use_library(so)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    oracle.set_threads(nthreads)
+    ref, reps, tc = None, 0, time.time()
+    while reps < 40 and (reps == 0 or time.time() - tc < 12.0):
+        ref = oracle.srfmg(f, LEVELS, K, S, list(J))
+        reps += 1
+    el = time.time() - tc
+    oracle.set_threads(1)
+    t1 = time.time()
+    oracle.srfmg(f, LEVELS, K, S, list(J))
+    el1 = time.time() - t1
+    oracle.set_threads(nthreads)
+    cpu = {"value": reps * N ** 3 / el, "unit": "DOF/s", "cores": nthreads, "kind": "oracle",
+           "sample": "%d SR-FMG FP64 solve(s) of the same 256^3 workload in %.1f s at %d threads; "
+                     "gcc -O3 -march=native -fopenmp on this host" % (reps, el, nthreads),
+           "one_thread_dof_per_s": N ** 3 / el1, "cpu_model": model}
+    parity = float(np.abs(fd_result - ref).max() / np.abs(ref).max()) if fd_result is not None else None
+    return cpu, parity
 
 
 def main():
@@ -200,18 +479,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 32^3 / 512^3 workloads, the V-cycle solver and the N sweep")
     ap.add_argument("--variants", default="sr,global,sr32r,batch96,batch96_fp32r")
     ap.add_argument("--counter-pass", action="store_true",
-                    help="run the workload for rocprofv3 --pmc (solves + calibration copy)")
+                    help="run one variant for rocprofv3 --pmc (solves + calibration copy)")
+    ap.add_argument("--variant", default="sr", choices=sorted(SPECS))
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two counter-pass CSVs")
-    ap.add_argument("--kernel", default="k_smooth_z<load,ns4,ry2>",
-                    help="profile label whose traffic --traffic-from extracts")
+                    help="add --variant to profiles/traffic.json from two counter-pass CSVs "
+                         "(--steps solves each)")
     ap.add_argument("--commands", default="", help="commands recorded in traffic.json")
     args = ap.parse_args()
     if args.traffic_from:
-        return traffic_from(args.traffic_from[0], args.traffic_from[1], args.kernel,
-                            os.path.join(ROOT, "profiles", "traffic.json"), args.commands)
+        return traffic_from(args.variant, args.steps, args.traffic_from[0], args.traffic_from[1],
+                            args.commands)
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
@@ -224,6 +505,7 @@ def main():
 
     from paper_1406_7808_amd import fmg
     from paper_1406_7808_amd import workloads as W
+    import oracle.exact as ex  # closed forms only (test infrastructure)
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -232,94 +514,34 @@ def main():
     fd = torch.from_numpy(f).to(dev)
     print("bench: inputs ready (%.1fs)" % (time.time() - t0), file=sys.stderr, flush=True)
 
-    specs = {
-        "sr": dict(sr_levels=K, segments=S, buffers=J),
-        "global": dict(),
-        "sr32r": dict(sr_levels=K, segments=S, buffers=J, precision="fp32_refined",
-                      refine_iters=2),
-    }
+    traffic = load_traffic()
     names = [v for v in args.variants.split(",") if v]
     batch_names = [v for v in names if v.startswith("batch96")]
     names = [v for v in names if v not in batch_names]
     res, outs, plans = {}, {}, {}
     for name in names:
-        plan = fmg.Plan(N, LEVELS, **specs[name])
+        ms, plan, u = time_solver(fmg, fd, SPECS[name], args.steps, args.warmup,
+                                  graph=not args.no_graph)
         plans[name] = plan
-        u = torch.empty_like(fd)
-        for _ in range(max(1, args.warmup)):
-            plan.execute(fd, u)
-        torch.cuda.synchronize()
-        graph = None
-        if not args.no_graph:
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                plan.execute(fd, u)
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph):
-                plan.execute(fd, u)
-            graph.replay()
-            torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            if graph is not None:
-                graph.replay()
-            else:
-                plan.execute(fd, u)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        meas = None
+        if traffic and name in traffic.get("variants", {}):
+            meas = traffic["variants"][name]["bytes_per_solve"]
         res[name] = {"ms": round(ms, 4), "dof_per_s": N ** 3 / (ms * 1e-3),
                      "workspace_MB": round(plan.workspace_bytes / 2 ** 20, 1),
-                     "graph": graph is not None}
+                     "graph": not args.no_graph}
+        res[name].update(hbm_fracs(fmg, N, SPECS[name], ms, meas))
         outs[name] = u.cpu().numpy()
         print("bench: %s %.3f ms/solve" % (name, ms), file=sys.stderr, flush=True)
-        del graph
 
     for name in batch_names:
         res[name] = batch_leg("fp32_refined" if name.endswith("fp32r") else "fp64", args)
         print("bench: %s %.3f ms per batch" % (name, res[name]["ms"]), file=sys.stderr, flush=True)
 
-    # dominant kernel of the headline solve: event-timed launches
     head = names[0]
-    plan = plans[head]
-    plan.profile(True)
-    u = torch.empty_like(fd)
-    for _ in range(3):
-        plan.execute(fd, u)
-    stats = plan.profile_read()
-    plan.profile(False)
-    # the dominant kernel: the instantiation (one rocprofv3 symbol) with the
-    # largest total time over all its levels and labels
-    by_kernel, label_of = {}, {}
-    for k, v in stats.items():
-        name = k.split("@")[0]
-        sym = symbol_pattern(name)
-        label_of.setdefault(sym, name)
-        a = by_kernel.setdefault(sym, [0, 0.0, 0.0])
-        for i in range(3):
-            a[i] += v[i]
-    sym = max(by_kernel, key=lambda k: by_kernel[k][1])
-    kern = label_of[sym]
-    launches, tot_ms, tot_bytes = by_kernel[sym]
-    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kern)
-    kernels = {k: {"launches": v[0] // 3, "ms_per_solve": round(v[1] / 3, 4),
-                   "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
-               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
-    roofline = {"bound": "hbm", "kernel": kern, "symbol": symbol_pattern(kern), "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "launches_per_solve": launches // 3,
-                "avg_launch_us": round(tot_ms / launches * 1e3, 2),
-                "bytes_per_launch": tot_bytes / launches}
+    roofline, kernels = dominant_kernel(fmg, plans[head], fd, traffic)
+    print("bench: dominant kernel %s" % roofline["kernel"], file=sys.stderr, flush=True)
 
     # accuracy against the closed-form discrete solution
-    import oracle.exact as ex  # closed forms only (test infrastructure)
     ud = W.fourier_field(N, kk, ex.modes_discrete(N, kk, aa))
     edisc = float(np.abs(ud - ucont).max())
     acc = {"e_disc": edisc}
@@ -329,21 +551,20 @@ def main():
     if "sr" in outs and "global" in outs:
         acc["e_r_sr_over_global"] = acc["sr"]["e_total"] / acc["global"]["e_total"]
 
+    extra = {}
+    if not args.no_extra:
+        extra["vcycle_rtol_1e-4"] = vcycle_leg(fmg, fd, ud, ucont, edisc, args)
+        print("bench: vcycle leg done", file=sys.stderr, flush=True)
+        extra["other_configs"] = other_configs(fmg, W, ex, args)
+        extra["convergence_N32_256"] = convergence_study(fmg, W, ex)
+        print("bench: convergence study done", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
-        import oracle
-        ref, reps, tc = None, 0, time.time()
-        # a bounded sample: whole solves until about 12 s have passed
-        while reps < 40 and (reps == 0 or time.time() - tc < 12.0):
-            ref = oracle.srfmg(f, LEVELS, K, S, list(J))
-            reps += 1
-        el = time.time() - tc
-        cpu = {"value": reps * N ** 3 / el, "unit": "DOF/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": "%d SR-FMG FP64 solve(s) of the same 256^3 workload, %.1f s" % (reps, el)}
-        if "sr" in outs:
-            acc["sr_parity_rel_vs_oracle"] = float(np.abs(outs["sr"] - ref).max()
-                                                   / np.abs(ref).max())
+        cpu, parity = cpu_leg(f, outs.get("sr"))
+        if parity is not None:
+            acc["sr_parity_rel_vs_oracle"] = parity
+        print("bench: cpu leg done", file=sys.stderr, flush=True)
 
     head_ms = res[head]["ms"]
     out = {
@@ -363,12 +584,15 @@ def main():
                    "sr_levels": K, "segments_per_dim": S, "buffers_finest_first": list(J),
                    "cycle": "F(1,2,2)", "rhs": "64 sine modes, seed 14067808",
                    "headline": head},
+        "hbm_frac_per_variant": {v: {"model": res[v]["hbm_frac_model"],
+                                     "measured": res[v]["hbm_frac_measured"]} for v in names},
         "variants": res,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
         "accuracy": acc,
     }
+    out.update(extra)
     for p in plans.values():
         p.close()
     print(json.dumps(out))

@@ -153,8 +153,10 @@ int32_t fmg_plan_checkpoints(fmg_plan *plan, double *const *out);
  * cycle count and the final max|f - L u| / max|f|.  Global FP64 plans only
  * (sr_levels == 0): FMG_ENOTSUP otherwise.  Synchronizes `stream` once per
  * cycle (the stopping test); rtol == 0 runs exactly maxit cycles and forms
- * the residual once, after the last (nothing waits between cycles).  The
- * norm partials live in the plan's workspace: the call allocates nothing.
+ * the residual once, after the last (nothing waits between cycles); rtol == 0
+ * with relres == NULL forms no residual and never synchronizes, so the call
+ * only enqueues work and may be captured into a HIP graph.  The norm
+ * partials live in the plan's workspace: the call allocates nothing.
  * FMG_EINVAL for null or overlapping f/u, rtol < 0, maxit < 0, or a residual
  * that is not finite (NaN or Inf in f or u). */
 int32_t fmg_plan_vcycles(fmg_plan *plan, const double *f, double *u, double rtol, int32_t maxit,

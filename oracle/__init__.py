@@ -35,13 +35,41 @@ def build(verbose=False):
     _lib = None
 
 
+def build_native(out_dir, verbose=False):
+    """The timing build: the same source with -O3 -march=native for the CPU
+    it is compiled on (so it is built where it runs, never shipped), into
+    out_dir/libfmg_oracle_native.so.  ISO C11 mode keeps gcc from contracting
+    multiply-adds, so its results equal the test build's.  Returns the path."""
+    so = os.path.join(out_dir, "libfmg_oracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+           "-o", so + ".tmp", _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(so + ".tmp", so)
+    return so
+
+
+def use_library(path):
+    """Load the oracle from another build of the same source (the timing
+    build); later calls of this module go to it."""
+    global _lib
+    _lib = None
+    _bind(ctypes.CDLL(path))
+    return _lib
+
+
 def lib():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         build()
-    L = ctypes.CDLL(_SO)
+    return _bind(ctypes.CDLL(_SO))
+
+
+def _bind(L):
+    global _lib
     i, d = ctypes.c_int, ctypes.c_double
     L.orc_fmg.argtypes = [_dp, i, i, i, i, i, _dp]
     L.orc_srfmg.argtypes = [_dp, i, i, i, i, _ip, i, i, i, _dp]
@@ -61,6 +89,8 @@ def lib():
     L.orc_interp.restype = None
     L.orc_coarse_solve.argtypes = [_dp, i, _dp]
     L.orc_threads.argtypes = []
+    L.orc_set_threads.argtypes = [i]
+    L.orc_set_threads.restype = None
     _lib = L
     return L
 
@@ -82,6 +112,10 @@ def _check(st):
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def fmg(f, levels, alpha=1, nu1=2, nu2=2):

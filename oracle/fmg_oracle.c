@@ -590,6 +590,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Threads for later parallel loops (results do not depend on it). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Plain global FMG F(alpha, nu1, nu2) (Fig. 2).  f, u: N^3, x fastest. */
 int orc_fmg(const double *f, int N, int L, int alpha, int nu1, int nu2, double *u) {
   if (!valid_levels(N, L)) return -1;

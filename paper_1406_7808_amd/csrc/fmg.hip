@@ -1536,7 +1536,10 @@ static int32_t norms(const double* a, const double* b, int32_t n, int mode, doub
 // oracle's iterated V-cycles); returns the cycle count, or -1 when the
 // residual is not finite (NaN or Inf in f or u).  rtol == 0 runs exactly
 // maxit cycles and forms the residual once, after the last, so that nothing
-// waits on the host between cycles.  The norms' partials live in the plan.
+// waits on the host between cycles; with relres == NULL as well it forms no
+// residual and never waits (every step is a launch or a device copy on s,
+// so the call can be captured into a graph).  The norms' partials live in
+// the plan.
 static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, int maxit,
                         double* relres, hipStream_t s) {
   const int N = P->N, L = P->L;
@@ -1551,10 +1554,18 @@ static int vcycle_solve(fmg_plan* P, const double* f, double* u, double rtol, in
   double* part = P->vpart;
   double* res = part + 2 * nb;
   double h[4];
+  const bool fixed = rtol == 0.0;
+  if (fixed && !relres) {
+    for (int it = 0; it < maxit; ++it) E.vcycle_global(L - 1, f);
+    if (H.u[L - 1] != u)
+      hipcheck(hipMemcpyAsync(u, H.u[L - 1], sizeof(double) * (size_t)cube(N),
+                              hipMemcpyDeviceToDevice, s),
+               "hipMemcpyAsync");
+    return maxit;
+  }
   hipcheck(norms_launch(f, f, N, 2, part, res + 2, s), "norms");
   int it = 0;
   double rn = 0.0, fn = 0.0;
-  const bool fixed = rtol == 0.0;
   for (;;) {
     if (fixed && it < maxit) {
       E.vcycle_global(L - 1, f);

@@ -231,17 +231,19 @@ class Plan:
         t = Tuning(**{**self.tuning, **kw})
         _check(lib().fmg_plan_set_tuning(self._h, ctypes.byref(t)))
 
-    def vcycles(self, f, u, rtol=1e-4, maxit=50, stream=None):
+    def vcycles(self, f, u, rtol=1e-4, maxit=50, stream=None, residual=True):
         """V(nu1, nu2) cycles from the guess in u (updated in place) until
         max|f - L u| <= rtol max|f| or maxit cycles; returns (cycles, relres).
         Global FP64 plans only.  Synchronizes the stream once per cycle;
-        rtol=0 runs exactly maxit cycles with one residual check at the end."""
+        rtol=0 runs exactly maxit cycles with one residual check at the end;
+        rtol=0 with residual=False only enqueues the cycles (no residual, no
+        synchronization, capturable into a graph) and returns (maxit, None)."""
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
         _check(lib().fmg_plan_vcycles(self._h, _dev(f, self.N), _dev(u, self.N), float(rtol),
-                                      int(maxit), ctypes.byref(it), ctypes.byref(rr),
-                                      _stream(stream)))
-        return it.value, rr.value
+                                      int(maxit), ctypes.byref(it),
+                                      ctypes.byref(rr) if residual else None, _stream(stream)))
+        return it.value, (rr.value if residual else None)
 
     def profile(self, enable=True):
         """Start (or stop) per-launch event timing; clears pending records."""
