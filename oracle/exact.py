@@ -42,3 +42,44 @@ def sine_discrete(N):
 def modes_discrete(N, k, a):
     """Coefficients a_m / lambda_h(k_m) of the discrete solution."""
     return a / eigenvalue(k, N)
+
+
+# --- the 27-point finite volume operator of the paper's model problem -------
+#
+# On a box of n0 x n1 x n2 cubic cells of size h with odd-reflection ghosts,
+# the operator is h^-2 sum_d D2_d W_e W_f with the 1D second difference D2
+# and the face-average weights W = (1/24, 11/12, 1/24).  Both 1D factors have
+# the sine modes sin(k pi (i + 1/2) / n), k = 1..n, as eigenvectors, with
+# eigenvalues -4 sin^2(k pi / (2n)) and 11/12 + (1/12) cos(k pi / n).
+
+FV27_W0 = 11.0 / 12.0
+FV27_W1 = 1.0 / 24.0
+
+
+def fv27_factors(k, n, h):
+    """1D eigenvalues (second difference / h^2, face weights) of mode k on n cells."""
+    k = np.asarray(k, dtype=np.float64)
+    mu = -(4.0 / h ** 2) * np.sin(k * math.pi / (2.0 * n)) ** 2
+    om = FV27_W0 + 2.0 * FV27_W1 * np.cos(k * math.pi / n)
+    return mu, om
+
+
+def fv27_eigenvalue(k, n, h):
+    """Eigenvalue of the mode with wavenumbers k = (k0, k1, k2) on extents n."""
+    m0, o0 = fv27_factors(k[0], n[0], h)
+    m1, o1 = fv27_factors(k[1], n[1], h)
+    m2, o2 = fv27_factors(k[2], n[2], h)
+    return m0 * o1 * o2 + o0 * m1 * o2 + o0 * o1 * m2
+
+
+def fv27_dst_solve(f, h):
+    """u = L^{-1} f for the 27-point operator, f indexed [z, y, x], by DST-II."""
+    n2, n1, n0 = f.shape
+    F = scipy.fft.dstn(f, type=2, norm="ortho", workers=-1)
+    m0, o0 = fv27_factors(np.arange(1, n0 + 1), n0, h)
+    m1, o1 = fv27_factors(np.arange(1, n1 + 1), n1, h)
+    m2, o2 = fv27_factors(np.arange(1, n2 + 1), n2, h)
+    lam = (m0[None, None, :] * o1[None, :, None] * o2[:, None, None]
+           + o0[None, None, :] * m1[None, :, None] * o2[:, None, None]
+           + o0[None, None, :] * o1[None, :, None] * m2[:, None, None])
+    return scipy.fft.idstn(F / lam, type=2, norm="ortho", workers=-1)

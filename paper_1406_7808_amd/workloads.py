@@ -82,6 +82,35 @@ def polynomial(N):
     return f, u
 
 
+def paper_model(m, R=(2.0, 1.0, 1.0)):
+    """The model problem of the paper (Sec. 5.1) on [0,2] x [0,1] x [0,1]
+    with cubic cells h = 1/m (2m x m x m cells): u = prod_i (x_i^4 - R_i^2
+    x_i^2), zero on the boundary, and f = Laplacian u, both at cell centers.
+    Returns (f, u, h), arrays indexed [z, y, x] of shape (m, m, 2m)."""
+    h = 1.0 / m
+    x = (np.arange(2 * m, dtype=np.float64) + 0.5) * h
+    y = (np.arange(m, dtype=np.float64) + 0.5) * h
+    g = [x ** 4 - R[0] ** 2 * x ** 2, y ** 4 - R[1] ** 2 * y ** 2, y ** 4 - R[2] ** 2 * y ** 2]
+    d2 = [12.0 * x ** 2 - 2.0 * R[0] ** 2, 12.0 * y ** 2 - 2.0 * R[1] ** 2,
+          12.0 * y ** 2 - 2.0 * R[2] ** 2]
+    u = _outer3(g[2], g[1], g[0])
+    f = _outer3(g[2], g[1], d2[0]) + _outer3(g[2], d2[1], g[0]) + _outer3(d2[2], g[1], g[0])
+    return np.ascontiguousarray(f), np.ascontiguousarray(u), h
+
+
+def buffer_schedule(A, B, K):
+    """Eq. 5: J_k = 2 floor((A + B (K - k)) / 2) for the SR levels k = 1..K,
+    returned finest level (k = K) first."""
+    return [2 * ((A + B * (K - k)) // 2) for k in range(K, 0, -1)]
+
+
+def max_buffer_schedule(J1, K):
+    """The maximum buffer schedule (Sec. 5.2): J_1 on the coarsest SR level and
+    every finer compute region the refinement of the next coarser one,
+    J_k = 2^(k-1) J_1; finest level first."""
+    return [J1 * 2 ** (k - 1) for k in range(K, 0, -1)]
+
+
 def random_field(N, seed):
     """Uniform(-1, 1) values, for operator-level checks."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(N, N, N))
