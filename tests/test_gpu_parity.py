@@ -13,6 +13,7 @@ import torch
 
 import oracle
 import oracle.exact as ex
+import refined_gap
 from paper_1406_7808_amd import fmg
 from paper_1406_7808_amd import workloads as W
 
@@ -285,18 +286,8 @@ def test_vcycles_to_tolerance():
 
 # --- mixed precision --------------------------------------------------------------
 
-def _fp32_gap(edisc, ref):
-    """Allowed distance between the FP32-refined solve and the oracle's FP64
-    run of the same outer iteration.  The first FP32 solve stores u itself in
-    FP32, leaving rounding noise of a few eps32 * |u| (eps32 = 6e-8) that each
-    FP64-residual correction shrinks only by the FMG contraction, so after two
-    corrections the gap is bounded by about 1e-6 |u|; on rough solutions the
-    algebraic-error term 1e-3 e_disc dominates."""
-    return 1e-3 * edisc + 1e-6 * np.abs(ref).max()
-
-
 @pytest.mark.parametrize("N,L,K,S,J", [(64, 6, 2, 2, [2, 2]), (64, 6, 0, 1, []),
-                                        (256, 8, 3, 8, [2, 4, 6])])
+                                        (128, 7, 3, 4, [2, 4, 6]), (256, 8, 3, 8, [2, 4, 6])])
 def test_fp32_refined_within_discretization_error(N, L, K, S, J):
     _say("fp32r", N, L, K, S, J)
     f, uc, (k, a) = W.fourier(N)
@@ -305,10 +296,8 @@ def test_fp32_refined_within_discretization_error(N, L, K, S, J):
     u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J, precision="fp32_refined",
                   refine_iters=2).cpu().numpy()
     assert np.abs(u - ud).max() <= 1.0 * edisc
-    # the same outer iteration run entirely in FP64 by the oracle
-    ref = oracle.srfmg_refined(f, L, K, S, J, iters=2) if K else None
-    if ref is not None:
-        assert np.abs(u - ref).max() <= _fp32_gap(edisc, ref)
+    # against the same outer iteration run entirely in FP64 by the oracle
+    refined_gap.check(f, ud, u, L, K, S, J, iters=2)
 
 
 def test_fp32_refined_512_polynomial():
@@ -324,8 +313,7 @@ def test_fp32_refined_512_polynomial():
     e = np.abs(u - ud).max()
     _say("512 e_alg / e_disc = %.3f" % (e / edisc))
     assert e <= 1.0 * edisc
-    ref = oracle.srfmg_refined(f, L, K, S, J, iters=2)
-    assert np.abs(u - ref).max() <= _fp32_gap(edisc, ref)
+    refined_gap.check(f, ud, u, L, K, S, J, iters=2)
 
 
 # --- determinism and plan reuse ---------------------------------------------------
