@@ -19,7 +19,9 @@ library's schedule model) and, where committed counter readings of the same
 kernel sources exist, measured HBM bytes per solve, each over its time.
 
 Also reported, outside the timed region: the same three solvers on the 32^3
-sine and 512^3 polynomial workloads; the V-cycle solver to a relative
+sine and 512^3 polynomial workloads; the paper's own model problem (27-point
+finite volume stencil, Chebyshev smoothers, 512 x 256 x 256 cells, global and
+SR); the V-cycle solver to a relative
 residual of 1e-4; error and residual of every solver for N = 32..256; the
 dominant kernel's roofline (HIP events around each of its launches, with the
 stream held by a sleep kernel until every launch is queued); the CPU
@@ -59,9 +61,13 @@ SPECS = variant_specs(LEVELS, K, S, J)
 
 
 def source_hash():
+    """Hash of the 7-point solver's sources (the model-problem solver,
+    fv27.hip, builds none of its kernels)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1406_7808_amd", "csrc")
     for name in sorted(os.listdir(d)):
+        if name.startswith("fv27"):
+            continue
         with open(os.path.join(d, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -435,6 +441,44 @@ def convergence_study(fmg, W, ex):
     return rows
 
 
+def fv27_leg(args):
+    """The paper's own model problem (Sec. 5.1): 27-point finite volume
+    stencil, Chebyshev smoothers F(1,2,2), trilinear prolongation, on
+    [0,2] x [0,1]^2 with 512 x 256 x 256 cells, u = prod(x_i^4 - R_i^2 x_i^2);
+    global FMG and SR with the 4 x 2 x 2 segment grid on the 4 finest levels
+    (8^3 genuine transition cells per segment), buffers from Eq. 5 with A = 4,
+    B = 1.  Graph-replayed solves; e_r = e_SR / e_conv as in Tables 1-3."""
+    import numpy as np
+    import torch
+    from paper_1406_7808_amd import fv27
+    from paper_1406_7808_amd import workloads as W
+    m, K, S = 256, 4, (4, 2, 2)
+    J = W.buffer_schedule(4, 1, K)
+    f, uc, h = W.paper_model(m)
+    L = int(math.log2(m)) + 1
+    n = (2 * m, m, m)
+    fd = torch.from_numpy(f).cuda()
+    out = {"cells": 2 * m ** 3, "levels": L, "sr_levels": K, "segments": list(S),
+           "buffers_finest_first": J, "degrees": [2, 2, 1]}
+    errs = {}
+    for name, kw in (("global", {}), ("sr", dict(sr_levels=K, segments=S, buffers=J))):
+        plan = fv27.Plan(n, h, L, **kw)
+        u = torch.empty_like(fd)
+        ms = time_graph(lambda: plan.execute(fd, u), max(3, args.steps // 2), args.warmup)
+        launches, model_bytes = plan.model()
+        errs[name] = float(np.abs(u.cpu().numpy() - uc).max())
+        out[name] = {"ms": round(ms, 4), "dof_per_s": 2 * m ** 3 / (ms * 1e-3),
+                     "launches": launches, "model_bytes_per_solve": model_bytes,
+                     "model_B_per_DOF": round(model_bytes / (2 * m ** 3), 1),
+                     "hbm_frac_model": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "e_total": errs[name],
+                     "workspace_MB": round(plan.workspace_bytes / 2 ** 20, 1)}
+        plan.close()
+        print("bench: fv27 %s %.3f ms/solve" % (name, ms), file=sys.stderr, flush=True)
+    out["e_r"] = errs["sr"] / errs["global"]
+    return out
+
+
 def cpu_leg(f, fd_result):
     """The oracle's SR solve of the 256^3 workload, built for this host's CPU
     (-O3 -march=native), at all OpenMP threads for about 12 s and at one
@@ -558,6 +602,7 @@ def main():
         extra["other_configs"] = other_configs(fmg, W, ex, args)
         extra["convergence_N32_256"] = convergence_study(fmg, W, ex)
         print("bench: convergence study done", file=sys.stderr, flush=True)
+        extra["paper_model_fv27"] = fv27_leg(args)
 
     cpu = None
     if not args.no_cpu:

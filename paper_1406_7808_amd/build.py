@@ -1,10 +1,12 @@
-"""Build the HIP library paper_1406_7808_amd/libfmg.so for gfx950 with hipcc."""
+"""Build the HIP library paper_1406_7808_amd/libfmg.so for gfx950 with hipcc:
+the 7-point solver (fmg.hip) and the paper's 27-point model problem
+(fv27.hip) in one shared library."""
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "fmg.hip")
+SRC = [os.path.join(HERE, "csrc", "fmg.hip"), os.path.join(HERE, "csrc", "fv27.hip")]
 OUT = os.path.join(HERE, "libfmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -17,7 +19,7 @@ FLAGS = [
 
 
 def build(verbose=False):
-    cmd = [HIPCC] + FLAGS + ["-o", OUT + ".tmp", SRC]
+    cmd = [HIPCC] + FLAGS + ["-o", OUT + ".tmp"] + SRC
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,1022 @@
+// fv27.hip -- FAS full multigrid with segmental refinement for the paper's
+// own model problem (Sec. 5.1 of "Segmental Refinement: A Multigrid Technique
+// for Data Locality", arXiv:1406.7808) on gfx950: a box of cubic cells, the
+// 27-point finite volume Laplacian, Chebyshev smoothers, trilinear
+// prolongation for both the FMG and the V-cycle, segments as an s0 x s1 x s2
+// array of cubic subdomains (the paper's process grid).
+//
+// The operator has tensor-product form: L = h^-2 (D2_x W_y W_z + W_x D2_y W_z
+// + W_x W_y D2_z) with D2 = (1, -2, 1) and the face-average weights
+// W = (w1, w0, w1) = (1/24, 11/12, 1/24).  Grouping by z gives
+//   L u(z) = h^-2 [ W_z P + D2_z Q ](z),
+//   P = (D2_x W_y + W_x D2_y) u,  Q = W_x W_y u   (9-point, in one xy plane),
+// so the smoothing kernel marches an xy tile through z, forms P and Q of each
+// plane from the plane staged in LDS (9 reads give both), keeps the last
+// three planes' P and Q in registers and combines them: 9 LDS reads per cell
+// instead of 27.  A ghost beyond a wall is the odd reflection of the interior
+// cell, per dimension, so a plane beyond a z wall is minus its mirror and
+// its P and Q are minus the mirror's.
+//
+// Storage: a global level is one n0 x n1 x n2 array (x fastest).  An SR
+// level holds one box per segment covering its compute region C and one
+// ghost layer (the frozen GSR cells inside the domain); box q sits at q * box
+// with fixed extents m[d] = min(n[d], g + 2J) + 2 (boxes of clipped segments
+// leave their tail unused).  Each level has two copies of u: a Chebyshev
+// step is a Jacobi-type update and reads one copy while writing the other on
+// C.  Ghost cells change only under prolongation, which writes both copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fmg.h"
+#include "../../include/fv27.h"
+
+namespace fv {
+
+constexpr double kW0 = 11.0 / 12.0;
+constexpr double kW1 = 1.0 / 24.0;
+constexpr int kTX = 32, kTY = 8, kThreads = kTX * kTY;  // march tile
+constexpr int kBlock = 256;                              // per-cell kernels
+constexpr int kMaxCoarse = 512;                          // cells of the coarsest level
+
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+struct hip_error {
+  std::string what;
+};
+
+static void hipcheck(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw hip_error{std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// ---------------------------------------------------------------------------
+// level geometry
+// ---------------------------------------------------------------------------
+
+struct Geo {
+  int n[3];       // level extents
+  int S[3];       // segments per dimension (1,1,1 for a global level)
+  int g;          // genuine edge of a segment (cubic)
+  int J;          // buffer width
+  int m[3];       // storage extents of one box
+  int sr;         // 1: segment boxes with a ghost layer; 0: one global array
+  long long box;  // cells of one box
+};
+
+static Geo global_geo(const int n[3]) {
+  Geo G;
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = n[d];
+    G.S[d] = 1;
+    G.m[d] = n[d];
+  }
+  G.g = 0;
+  G.J = 0;
+  G.sr = 0;
+  G.box = (long long)n[0] * n[1] * n[2];
+  return G;
+}
+
+static Geo seg_geo(const int n[3], const int S[3], int J) {
+  Geo G;
+  G.g = n[0] / S[0];
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = n[d];
+    G.S[d] = S[d];
+    G.m[d] = std::min(n[d], G.g + 2 * J) + 2;
+  }
+  G.J = J;
+  G.sr = 1;
+  G.box = (long long)G.m[0] * G.m[1] * G.m[2];
+  return G;
+}
+
+static int nseg(const Geo& G) { return G.S[0] * G.S[1] * G.S[2]; }
+
+// compute region [clo, chi) and storage origin slo of segment q
+__host__ __device__ inline void seg_region(const Geo& G, int q, int clo[3], int chi[3],
+                                           int slo[3]) {
+  int p[3] = {q % G.S[0], (q / G.S[0]) % G.S[1], q / (G.S[0] * G.S[1])};
+  for (int d = 0; d < 3; ++d) {
+    if (G.sr) {
+      int a = p[d] * G.g - G.J, b = (p[d] + 1) * G.g + G.J;
+      clo[d] = a < 0 ? 0 : a;
+      chi[d] = b > G.n[d] ? G.n[d] : b;
+      slo[d] = clo[d] - 1;
+    } else {
+      clo[d] = 0;
+      chi[d] = G.n[d];
+      slo[d] = 0;
+    }
+  }
+}
+
+// genuine region of segment q
+__host__ __device__ inline void seg_genuine(const Geo& G, int q, int vlo[3], int vhi[3]) {
+  int p[3] = {q % G.S[0], (q / G.S[0]) % G.S[1], q / (G.S[0] * G.S[1])};
+  for (int d = 0; d < 3; ++d) {
+    int e = G.n[d] / G.S[d];
+    vlo[d] = p[d] * e;
+    vhi[d] = (p[d] + 1) * e;
+  }
+}
+
+__host__ __device__ inline long long sidx(const Geo& G, int q, const int slo[3], int x, int y,
+                                          int z) {
+  return (long long)q * G.box +
+         ((long long)(z - slo[2]) * G.m[1] + (y - slo[1])) * G.m[0] + (x - slo[0]);
+}
+
+// odd reflection of one index into [0, n); returns the sign
+__device__ inline double mirror(int n, int& i) {
+  if (i < 0) {
+    i = -1 - i;
+    return -1.0;
+  }
+  if (i >= n) {
+    i = 2 * n - 1 - i;
+    return -1.0;
+  }
+  return 1.0;
+}
+
+// value of cell (x,y,z) of level storage v (segment q), ghosts beyond a wall
+// by odd reflection
+template <class T>
+__device__ inline double value(const T* v, const Geo& G, int q, const int slo[3], int x, int y,
+                               int z) {
+  double s = mirror(G.n[0], x) * mirror(G.n[1], y) * mirror(G.n[2], z);
+  return s * (double)v[sidx(G, q, slo, x, y, z)];
+}
+
+// 27-point L v at cell (x,y,z), read directly (per-cell kernels on small or
+// coarse levels); same grouping as the march: W_z P + D2_z Q
+__device__ inline double apply_L_direct(const double* v, const Geo& G, int q, const int slo[3],
+                                        int x, int y, int z, double inv_h2) {
+  double P[3], Q[3];
+  for (int c = 0; c < 3; ++c) {
+    double a[3][3];
+    for (int b = 0; b < 3; ++b)
+      for (int e = 0; e < 3; ++e) a[b][e] = value(v, G, q, slo, x + e - 1, y + b - 1, z + c - 1);
+    const double ctr = a[1][1];
+    const double face = (a[1][0] + a[1][2]) + (a[0][1] + a[2][1]);
+    const double corner = (a[0][0] + a[0][2]) + (a[2][0] + a[2][2]);
+    P[c] = -4.0 * kW0 * ctr + (kW0 - 2.0 * kW1) * face + 2.0 * kW1 * corner;
+    Q[c] = kW0 * kW0 * ctr + kW0 * kW1 * face + kW1 * kW1 * corner;
+  }
+  return (kW1 * (P[0] + P[2]) + kW0 * P[1] + (Q[0] + Q[2]) - 2.0 * Q[1]) * inv_h2;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+struct MarchArgs {
+  Geo G;
+  const double* u;    // input copy
+  double* out;        // output copy (Chebyshev step) or residual array
+  const double* rhs;  // right-hand side: level storage, or a global array
+  int rhs_global;     // rhs indexed as a global n0 x n1 x n2 array
+  int mode;           // 0: out = u - c (rhs - L u) on C; 1: out = rhs - L u on C;
+                      // 2: out = L u on C (rhs unused)
+  double c;
+  double inv_h2;
+  int tiles_x, zchunk;
+};
+
+// An xy tile of kTX x kTY columns of one segment's compute region marches a
+// z chunk.  Each step stages one plane of u (tile + 1-cell halo, ghosts and
+// reflections resolved) in LDS, forms that plane's P and Q, and finishes the
+// plane one below.  Double-buffered planes: one barrier per step.
+__global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
+  const Geo& G = A.G;
+  const int q = blockIdx.z;
+  int clo[3], chi[3], slo[3];
+  seg_region(G, q, clo, chi, slo);
+  const int tx = blockIdx.x % A.tiles_x, ty = blockIdx.x / A.tiles_x;
+  const int x0 = clo[0] + tx * kTX, y0 = clo[1] + ty * kTY;
+  const int z0 = clo[2] + blockIdx.y * A.zchunk;
+  if (x0 >= chi[0] || y0 >= chi[1] || z0 >= chi[2]) return;  // uniform over the block
+  const int z1 = min(chi[2], z0 + A.zchunk);
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool active = x < chi[0] && y < chi[1];
+  // halo columns beyond C + 1 are never needed (and lie outside the box)
+  const int xh = min(x0 + kTX, chi[0]), yh = min(y0 + kTY, chi[1]);
+
+  __shared__ double plane[2][kTY + 2][kTX + 2];
+  double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0, c1 = 0, c2 = 0;
+  const int nsteps = z1 - z0 + 2;
+  for (int s = 0; s < nsteps; ++s) {
+    const int zl = z0 - 1 + s;
+    double(*pl)[kTX + 2] = plane[s & 1];
+    for (int i = threadIdx.x; i < (kTX + 2) * (kTY + 2); i += kThreads) {
+      const int xx = i % (kTX + 2), yy = i / (kTX + 2);
+      const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+      double v = 0.0;
+      if (gx <= xh && gy <= yh) v = value(A.u, G, q, slo, gx, gy, zl);
+      pl[yy][xx] = v;
+    }
+    __syncthreads();
+    const double ctr = pl[ly + 1][lx + 1];
+    const double face = (pl[ly + 1][lx] + pl[ly + 1][lx + 2]) + (pl[ly][lx + 1] + pl[ly + 2][lx + 1]);
+    const double corner = (pl[ly][lx] + pl[ly][lx + 2]) + (pl[ly + 2][lx] + pl[ly + 2][lx + 2]);
+    P0 = P1;
+    P1 = P2;
+    P2 = -4.0 * kW0 * ctr + (kW0 - 2.0 * kW1) * face + 2.0 * kW1 * corner;
+    Q0 = Q1;
+    Q1 = Q2;
+    Q2 = kW0 * kW0 * ctr + kW0 * kW1 * face + kW1 * kW1 * corner;
+    c1 = c2;
+    c2 = ctr;
+    if (s >= 2 && active) {
+      const int zc = zl - 1;
+      const double Lu = (kW1 * (P0 + P2) + kW0 * P1 + (Q0 + Q2) - 2.0 * Q1) * A.inv_h2;
+      const long long id = sidx(G, q, slo, x, y, zc);
+      if (A.mode == 2) {
+        A.out[id] = Lu;
+      } else {
+        const double f =
+            A.rhs_global ? A.rhs[((long long)zc * G.n[1] + y) * G.n[0] + x] : A.rhs[id];
+        const double r = f - Lu;
+        A.out[id] = A.mode ? r : c1 - A.c * r;
+      }
+    }
+  }
+}
+
+// mean of the 8 children of coarse cell (I,J,K) of fine storage v
+__device__ inline double mean8(const double* v, const Geo& F, int q, const int slo[3], int I,
+                               int J, int K) {
+  double s = 0.0;
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) s += v[sidx(F, q, slo, 2 * I + a, 2 * J + b, 2 * K + c)];
+  return s / 8.0;
+}
+
+struct RestrictArgs {
+  Geo F, C;          // fine and coarse geometry
+  const double* fu;  // fine u (or f)
+  const double* fr;  // fine residual (null: restrict fu only)
+  double* cu;        // coarse u (or f)
+  double* cr;        // coarse restricted residual
+  int target;        // 0: every coarse cell (global to global); 1: F = C_fine / 2 of
+                     // each segment into its coarse box; 2: genuine coarse cells of
+                     // each segment into the global coarse level (owner computes)
+  int ex[3];         // extents of the per-segment index space
+};
+
+__global__ void __launch_bounds__(kBlock) k_fv_restrict(RestrictArgs A) {
+  const int q = blockIdx.y;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)A.ex[0] * A.ex[1] * A.ex[2]) return;
+  int o[3] = {(int)(t % A.ex[0]), (int)((t / A.ex[0]) % A.ex[1]), (int)(t / ((long long)A.ex[0] * A.ex[1]))};
+  int flo[3], fhi[3], fslo[3];
+  seg_region(A.F, q, flo, fhi, fslo);
+  int lo[3], hi[3];
+  if (A.target == 1) {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = flo[d] / 2;
+      hi[d] = fhi[d] / 2;
+    }
+  } else if (A.target == 2) {
+    int vlo[3], vhi[3];
+    seg_genuine(A.F, q, vlo, vhi);
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = vlo[d] / 2;
+      hi[d] = vhi[d] / 2;
+    }
+  } else {
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = 0;
+      hi[d] = A.C.n[d];
+    }
+  }
+  const int I = lo[0] + o[0], J = lo[1] + o[1], K = lo[2] + o[2];
+  if (I >= hi[0] || J >= hi[1] || K >= hi[2]) return;
+  int clo[3], chi[3], cslo[3];
+  seg_region(A.C, A.target == 1 ? q : 0, clo, chi, cslo);
+  const long long cid = sidx(A.C, A.target == 1 ? q : 0, cslo, I, J, K);
+  A.cu[cid] = mean8(A.fu, A.F, q, fslo, I, J, K);
+  if (A.fr) A.cr[cid] = mean8(A.fr, A.F, q, fslo, I, J, K);
+}
+
+struct FasArgs {
+  Geo C;             // coarse level
+  Geo F;             // the finer level (for the region F = C_fine / 2)
+  const double* u;   // coarse u (restricted on F)
+  const double* rr;  // restricted residual (valid on F, or everywhere if global)
+  double* rhs;       // coarse right-hand side (on C)
+  double* t;         // copy of u (whole storage inside the domain)
+  double inv_h2;
+};
+
+// rhs = (R res on F, 0 on C \ F) + L_c u on C; t = u on C and ghosts
+__global__ void __launch_bounds__(kBlock) k_fv_fas(FasArgs A) {
+  const int q = blockIdx.y;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const Geo& G = A.C;
+  if (t >= G.box) return;
+  int clo[3], chi[3], slo[3];
+  seg_region(G, q, clo, chi, slo);
+  const int x = slo[0] + (int)(t % G.m[0]), y = slo[1] + (int)((t / G.m[0]) % G.m[1]),
+            z = slo[2] + (int)(t / ((long long)G.m[0] * G.m[1]));
+  if (x < 0 || y < 0 || z < 0 || x >= G.n[0] || y >= G.n[1] || z >= G.n[2]) return;
+  if (x > chi[0] || y > chi[1] || z > chi[2]) return;  // beyond this segment's box
+  const long long id = q * G.box + t;
+  A.t[id] = A.u[id];
+  if (x < clo[0] || y < clo[1] || z < clo[2] || x >= chi[0] || y >= chi[1] || z >= chi[2]) return;
+  bool inF = true;
+  if (G.sr) {
+    int flo[3], fhi[3], fslo[3];
+    seg_region(A.F, q, flo, fhi, fslo);
+    inF = x >= flo[0] / 2 && x < fhi[0] / 2 && y >= flo[1] / 2 && y < fhi[1] / 2 &&
+          z >= flo[2] / 2 && z < fhi[2] / 2;
+  }
+  const double Lu = apply_L_direct(A.u, G, q, slo, x, y, z, A.inv_h2);
+  A.rhs[id] = (inF ? A.rr[id] : 0.0) + Lu;
+}
+
+struct ProlongArgs {
+  Geo F, C;          // fine (target) and coarse (source) geometry
+  int csrc_seg;      // 1: the coarse source is the same segment's box; 0: global
+  const double* w;   // coarse source (u for the FMG step; w for the correction)
+  const double* t;   // coarse t (correction only; null for the FMG step)
+  double* u0;        // fine copies, both written
+  double* u1;
+  int add;           // 0: u = P w; 1: u += P (w - t)
+};
+
+// trilinear prolongation onto every storage cell inside the domain (C and
+// the frozen ghosts): the FMG step, or the V-cycle correction
+__global__ void __launch_bounds__(kBlock) k_fv_prolong(ProlongArgs A) {
+  const int q = blockIdx.y;
+  const Geo& G = A.F;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= G.box) return;
+  int clo[3], chi[3], slo[3];
+  seg_region(G, q, clo, chi, slo);
+  const int x = slo[0] + (int)(t % G.m[0]), y = slo[1] + (int)((t / G.m[0]) % G.m[1]),
+            z = slo[2] + (int)(t / ((long long)G.m[0] * G.m[1]));
+  if (x < 0 || y < 0 || z < 0 || x >= G.n[0] || y >= G.n[1] || z >= G.n[2]) return;
+  if (x > chi[0] || y > chi[1] || z > chi[2]) return;
+  const int cq = A.csrc_seg ? q : 0;
+  int cclo[3], cchi[3], cslo[3];
+  seg_region(A.C, cq, cclo, cchi, cslo);
+  const int fi[3] = {x, y, z};
+  int p[3], o[3];
+  for (int d = 0; d < 3; ++d) {
+    p[d] = fi[d] >> 1;  // fi >= 0
+    o[d] = (fi[d] & 1) ? p[d] + 1 : p[d] - 1;
+  }
+  double s = 0.0;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const double wt = (cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
+        int a = cx ? o[0] : p[0], b = cy ? o[1] : p[1], c = cz ? o[2] : p[2];
+        const double sg = mirror(A.C.n[0], a) * mirror(A.C.n[1], b) * mirror(A.C.n[2], c);
+        const long long cid = sidx(A.C, cq, cslo, a, b, c);
+        const double v = A.add ? A.w[cid] - A.t[cid] : A.w[cid];
+        s += wt * (sg * v);
+      }
+  const long long id = q * G.box + t;
+  const double nv = A.add ? A.u0[id] + s : s;
+  A.u0[id] = nv;
+  A.u1[id] = nv;
+}
+
+// u = Ainv rhs on the coarsest level (one workgroup)
+__global__ void __launch_bounds__(kBlock) k_fv_coarse(const double* __restrict__ Ainv, int m,
+                                                     const double* __restrict__ rhs,
+                                                     double* __restrict__ u0,
+                                                     double* __restrict__ u1) {
+  __shared__ double r[kMaxCoarse];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) r[i] = rhs[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += Ainv[(long long)i * m + j] * r[j];
+    u0[i] = s;
+    u1[i] = s;
+  }
+}
+
+// genuine cells of the finest segments into the caller's u (or a global
+// level's copy into u)
+__global__ void __launch_bounds__(kBlock) k_fv_gather(double* __restrict__ out,
+                                                     const double* __restrict__ v, Geo G) {
+  const int q = blockIdx.y;
+  int vlo[3], vhi[3];
+  seg_genuine(G, q, vlo, vhi);
+  const int e[3] = {vhi[0] - vlo[0], vhi[1] - vlo[1], vhi[2] - vlo[2]};
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)e[0] * e[1] * e[2]) return;
+  const int x = vlo[0] + (int)(t % e[0]), y = vlo[1] + (int)((t / e[0]) % e[1]),
+            z = vlo[2] + (int)(t / ((long long)e[0] * e[1]));
+  int clo[3], chi[3], slo[3];
+  seg_region(G, q, clo, chi, slo);
+  out[((long long)z * G.n[1] + y) * G.n[0] + x] = v[sidx(G, q, slo, x, y, z)];
+}
+
+// ---------------------------------------------------------------------------
+// host: plan and schedule
+// ---------------------------------------------------------------------------
+
+struct Level {
+  Geo G;
+  double h;
+  double* u[2] = {nullptr, nullptr};  // two copies
+  int cur = 0;                        // copy holding the current iterate
+  double* rhs = nullptr;              // segment / coarse right-hand side
+  double* t = nullptr;                // copy of the restricted u
+  double* r = nullptr;                // residual, then restricted residual
+  double* f = nullptr;                // FMG right-hand side (global array)
+};
+
+}  // namespace fv
+
+struct fv27_plan {
+  fv27_params p;
+  std::vector<int32_t> J;
+  int device = 0;
+  int L = 0, K = 0, T = 0;
+  std::vector<fv::Level> lv;
+  std::vector<void*> allocs;
+  double* Ainv = nullptr;
+  int m0 = 0;
+  int64_t bytes = 0;
+  // schedule model of the last walk
+  int64_t launches = 0;
+  double model_bytes = 0.0;
+};
+
+namespace fv {
+
+static const char* check(const fv27_params* p) {
+  if (!p) return "params is NULL";
+  if (!(p->h > 0.0) || !std::isfinite(p->h)) return "h must be positive and finite";
+  if (p->levels < 1 || p->levels > 24) return "levels must be in [1, 24]";
+  long long m = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (p->n[d] < 1) return "every extent must be >= 1";
+    if ((p->n[d] >> (p->levels - 1)) << (p->levels - 1) != p->n[d])
+      return "every extent must be divisible by 2^(levels-1)";
+    m *= p->n[d] >> (p->levels - 1);
+  }
+  if (m > kMaxCoarse) return "the coarsest level must have at most 512 cells";
+  if ((long long)p->n[0] * p->n[1] * p->n[2] > (1ll << 33)) return "grid too large";
+  if (p->cheb_pre < 0 || p->cheb_pre > 8 || p->cheb_post < 0 || p->cheb_post > 8 ||
+      p->cheb_fmg < 0 || p->cheb_fmg > 8)
+    return "Chebyshev degrees must be in [0, 8]";
+  const int K = p->sr_levels;
+  if (K < 0 || K > p->levels - 1) return "sr_levels must be in [0, levels-1]";
+  if (K == 0) return nullptr;
+  if (!p->buffer_schedule) return "buffer_schedule is NULL";
+  for (int d = 0; d < 3; ++d) {
+    if (p->segments[d] < 1) return "segments must be >= 1";
+    if (p->n[d] % ((long long)p->segments[d] << K) != 0)
+      return "every extent must be divisible by segments << sr_levels";
+  }
+  if (p->n[0] / p->segments[0] != p->n[1] / p->segments[1] ||
+      p->n[0] / p->segments[0] != p->n[2] / p->segments[2])
+    return "segments must be cubic (n[d] / segments[d] equal for all d)";
+  for (int i = 0; i < K; ++i) {
+    const int j = p->buffer_schedule[i];
+    if (j < 0 || (j & 1)) return "buffer widths must be even and >= 0";
+    if (j > (1 << 20)) return "buffer width too large";
+    if (i + 1 < K && 2 * p->buffer_schedule[i + 1] < j)
+      return "each buffer width must be at least half the next finer one";
+  }
+  return nullptr;
+}
+
+// exact inverse of the coarsest operator (Gauss-Jordan with partial pivoting)
+static std::vector<double> coarse_inverse(const int n[3], double h) {
+  const int m = n[0] * n[1] * n[2];
+  std::vector<double> A((size_t)m * m, 0.0), I((size_t)m * m, 0.0);
+  auto refl = [](int nn, int& i) -> double {
+    if (i < 0) {
+      i = -1 - i;
+      return -1.0;
+    }
+    if (i >= nn) {
+      i = 2 * nn - 1 - i;
+      return -1.0;
+    }
+    return 1.0;
+  };
+  const double w[3] = {kW1, kW0, kW1};
+  const double d2[3] = {1.0, -2.0, 1.0};
+  for (int z = 0; z < n[2]; ++z)
+    for (int y = 0; y < n[1]; ++y)
+      for (int x = 0; x < n[0]; ++x) {
+        const int row = (z * n[1] + y) * n[0] + x;
+        for (int c = 0; c < 3; ++c)
+          for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+              const double coef =
+                  (d2[a] * w[b] * w[c] + w[a] * d2[b] * w[c] + w[a] * w[b] * d2[c]) / (h * h);
+              int i = x + a - 1, j = y + b - 1, k = z + c - 1;
+              const double s = refl(n[0], i) * refl(n[1], j) * refl(n[2], k);
+              A[(size_t)row * m + (k * n[1] + j) * n[0] + i] += s * coef;
+            }
+      }
+  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int best = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)best * m + c])) best = r;
+    if (best != c)
+      for (int t = 0; t < m; ++t) {
+        std::swap(A[(size_t)c * m + t], A[(size_t)best * m + t]);
+        std::swap(I[(size_t)c * m + t], I[(size_t)best * m + t]);
+      }
+    const double piv = A[(size_t)c * m + c];
+    for (int t = 0; t < m; ++t) {
+      A[(size_t)c * m + t] /= piv;
+      I[(size_t)c * m + t] /= piv;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double l = A[(size_t)r * m + c];
+      if (l == 0.0) continue;
+      for (int t = 0; t < m; ++t) {
+        A[(size_t)r * m + t] -= l * A[(size_t)c * m + t];
+        I[(size_t)r * m + t] -= l * I[(size_t)c * m + t];
+      }
+    }
+  }
+  return I;
+}
+
+static double cheb_root(int j, int k) {
+  const double pi = 3.14159265358979323846;
+  const double a = 48.0 / 121.0, b = 200.0 / 121.0;
+  return 0.5 * (a + b) + 0.5 * (b - a) * std::cos((2.0 * j - 1.0) * pi / (2.0 * k));
+}
+
+static unsigned blocks_for(long long cells) { return (unsigned)((cells + kBlock - 1) / kBlock); }
+
+// One solve's launches (or, with dry, only their count and bytes).
+struct Exec {
+  fv27_plan* P;
+  hipStream_t s;
+  bool dry;
+
+  void count(double bytes) {
+    P->launches += 1;
+    P->model_bytes += bytes;
+  }
+  void launched() {
+    if (!dry) hipcheck(hipGetLastError(), "kernel launch");
+  }
+
+  // cells of the compute regions of a level (all segments)
+  static double c_cells(const Geo& G) {
+    double s = 0.0;
+    for (int q = 0; q < nseg(G); ++q) {
+      int lo[3], hi[3], sl[3];
+      seg_region(G, q, lo, hi, sl);
+      s += (double)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    }
+    return s;
+  }
+  static double storage_cells(const Geo& G) {
+    double s = 0.0;
+    for (int q = 0; q < nseg(G); ++q) {
+      int lo[3], hi[3], sl[3];
+      seg_region(G, q, lo, hi, sl);
+      double c = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        int a = G.sr ? std::max(0, lo[d] - 1) : 0, b = G.sr ? std::min(G.n[d], hi[d] + 1) : G.n[d];
+        c *= (double)(b - a);
+      }
+      s += c;
+    }
+    return s;
+  }
+
+  // one march pass over level l: mode 0 Chebyshev step (cur -> other), mode 1
+  // residual into lv.r
+  void march(int l, const double* rhs, bool rhs_global, int mode, double c) {
+    Level& V = P->lv[l];
+    const Geo& G = V.G;
+    MarchArgs A;
+    A.G = G;
+    A.u = V.u[V.cur];
+    A.out = mode ? V.r : V.u[V.cur ^ 1];
+    A.rhs = rhs;
+    A.rhs_global = rhs_global ? 1 : 0;
+    A.mode = mode;
+    A.c = c;
+    A.inv_h2 = 1.0 / (V.h * V.h);
+    int ext[3];
+    if (G.sr) {
+      for (int d = 0; d < 3; ++d) ext[d] = std::min(G.n[d], G.g + 2 * G.J);
+    } else {
+      for (int d = 0; d < 3; ++d) ext[d] = G.n[d];
+    }
+    A.tiles_x = (ext[0] + kTX - 1) / kTX;
+    const int tiles_y = (ext[1] + kTY - 1) / kTY;
+    const long long cols = (long long)A.tiles_x * tiles_y * nseg(G);
+    // enough workgroups to fill the chip, chunks of at least 8 planes
+    int chunks = (int)std::max(1ll, std::min((long long)(ext[2] + 7) / 8, (2048 + cols - 1) / cols));
+    A.zchunk = (ext[2] + chunks - 1) / chunks;
+    chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
+    count(c_cells(G) * 24.0);
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_march, dim3((unsigned)(A.tiles_x * tiles_y), (unsigned)chunks,
+                                        (unsigned)nseg(G)),
+                       dim3(kThreads), 0, s, A);
+    launched();
+    if (mode == 0) V.cur ^= 1;
+  }
+
+  void cheb(int l, const double* rhs, bool rhs_global, int degree) {
+    Level& V = P->lv[l];
+    const double d = (121.0 / 24.0) / (V.h * V.h);
+    for (int j = 1; j <= degree; ++j) march(l, rhs, rhs_global, 0, 1.0 / (d * cheb_root(j, degree)));
+  }
+
+  // restriction of u (and the residual) from level l into level l-1
+  void restrict_level(int l, int target) {
+    Level& F = P->lv[l];
+    Level& C = P->lv[l - 1];
+    RestrictArgs A;
+    A.F = F.G;
+    A.C = C.G;
+    A.fu = F.u[F.cur];
+    A.fr = F.r;
+    A.cu = C.u[C.cur];
+    A.cr = C.r;
+    A.target = target;
+    int ex[3];
+    if (target == 0) {
+      for (int d = 0; d < 3; ++d) ex[d] = C.G.n[d];
+    } else if (target == 1) {
+      for (int d = 0; d < 3; ++d) ex[d] = std::min(F.G.n[d], F.G.g + 2 * F.G.J) / 2;
+    } else {
+      for (int d = 0; d < 3; ++d) ex[d] = F.G.g / 2;
+    }
+    for (int d = 0; d < 3; ++d) A.ex[d] = ex[d];
+    const long long cells = (long long)ex[0] * ex[1] * ex[2];
+    count((double)cells * nseg(F.G) * (16.0 * 8 + 16.0));
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_restrict, dim3(blocks_for(cells), (unsigned)nseg(F.G)), dim3(kBlock), 0,
+                       s, A);
+    launched();
+  }
+
+  void fas(int l) {  // coarse level l - 1 of fine level l
+    Level& F = P->lv[l];
+    Level& C = P->lv[l - 1];
+    FasArgs A;
+    A.C = C.G;
+    A.F = F.G;
+    A.u = C.u[C.cur];
+    A.rr = C.r;
+    A.rhs = C.rhs;
+    A.t = C.t;
+    A.inv_h2 = 1.0 / (C.h * C.h);
+    count(storage_cells(C.G) * 16.0 + c_cells(C.G) * 16.0);
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_fas, dim3(blocks_for(C.G.box), (unsigned)nseg(C.G)), dim3(kBlock), 0, s,
+                       A);
+    launched();
+  }
+
+  // FMG step (add = 0, source u of level l-1) or correction (add = 1)
+  void prolong(int l, int add) {
+    Level& F = P->lv[l];
+    Level& C = P->lv[l - 1];
+    ProlongArgs A;
+    A.F = F.G;
+    A.C = C.G;
+    A.csrc_seg = C.G.sr;
+    A.w = C.u[C.cur];
+    A.t = add ? C.t : nullptr;
+    A.u0 = F.u[F.cur];
+    A.u1 = F.u[F.cur ^ 1];
+    A.add = add;
+    const double fc = storage_cells(F.G);
+    count(fc * (add ? 24.0 : 16.0) + storage_cells(C.G) * (add ? 16.0 : 8.0));
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_prolong, dim3(blocks_for(F.G.box), (unsigned)nseg(F.G)), dim3(kBlock), 0,
+                       s, A);
+    launched();
+  }
+
+  void coarse_solve(const double* rhs) {
+    Level& V = P->lv[0];
+    count(P->m0 * 24.0 + (double)P->m0 * P->m0 * 8.0);
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_coarse, dim3(1), dim3(kBlock), 0, s, (const double*)P->Ainv, P->m0, rhs,
+                       V.u[0], V.u[1]);
+    launched();
+  }
+
+  // FAS V-cycle on global level l (Fig. 1)
+  void vcycle_global(int l, const double* rhs) {
+    Level& V = P->lv[l];
+    if (l == 0) {
+      coarse_solve(rhs);
+      return;
+    }
+    cheb(l, rhs, true, P->p.cheb_pre);
+    march(l, rhs, true, 1, 0.0);
+    restrict_level(l, 0);
+    fas(l);
+    vcycle_global(l - 1, P->lv[l - 1].rhs);
+    prolong(l, 1);
+    cheb(l, rhs, true, P->p.cheb_post);
+    (void)V;
+  }
+
+  // FAS V-cycle with segmental refinement on SR level l (Fig. 6); top is the
+  // level of the current FMG stage, whose right-hand side is the global f
+  void vcycle_sr(int l, int top) {
+    Level& V = P->lv[l];
+    const bool atop = l == top;
+    const double* rhs = atop ? V.f : V.rhs;
+    cheb(l, rhs, atop, P->p.cheb_pre);
+    march(l, rhs, atop, 1, 0.0);
+    if (l - 1 > P->T) {
+      restrict_level(l, 1);
+      fas(l);
+      vcycle_sr(l - 1, top);
+    } else {
+      restrict_level(l, 2);
+      fas(l);
+      vcycle_global(l - 1, P->lv[l - 1].rhs);
+    }
+    prolong(l, 1);
+    cheb(l, rhs, atop, P->p.cheb_post);
+  }
+
+  void f_hierarchy(const double* f) {
+    P->lv[P->L - 1].f = const_cast<double*>(f);
+    for (int l = P->L - 1; l > 0; --l) {
+      Level& F = P->lv[l];
+      Level& C = P->lv[l - 1];
+      RestrictArgs A;
+      A.F = global_geo(F.G.n);
+      A.C = global_geo(C.G.n);
+      A.fu = F.f;
+      A.fr = nullptr;
+      A.cu = C.f;
+      A.cr = nullptr;
+      A.target = 0;
+      for (int d = 0; d < 3; ++d) A.ex[d] = C.G.n[d];
+      const long long cells = (long long)A.ex[0] * A.ex[1] * A.ex[2];
+      count((double)cells * 72.0);
+      if (dry) continue;
+      hipLaunchKernelGGL(k_fv_restrict, dim3(blocks_for(cells), 1), dim3(kBlock), 0, s, A);
+      launched();
+    }
+  }
+
+  void solve(const double* f, double* u) {
+    const int L = P->L;
+    for (auto& V : P->lv) V.cur = 0;
+    f_hierarchy(f);
+    // global FMG stages 0..T (Fig. 2)
+    coarse_solve(P->lv[0].f);
+    for (int l = 1; l <= P->T; ++l) {
+      prolong(l, 0);
+      cheb(l, P->lv[l].f, true, P->p.cheb_fmg);
+      vcycle_global(l, P->lv[l].f);
+    }
+    // segment stages T+1..L-1 (Fig. 5)
+    for (int top = P->T + 1; top < L; ++top) {
+      prolong(top, 0);
+      cheb(top, P->lv[top].f, true, P->p.cheb_fmg);
+      vcycle_sr(top, top);
+    }
+    // output: the genuine cells of the finest level
+    Level& V = P->lv[L - 1];
+    const Geo& G = V.G;
+    const long long cells = G.sr ? (long long)G.g * G.g * G.g : G.box;
+    count((double)G.n[0] * G.n[1] * G.n[2] * 16.0);
+    if (dry) return;
+    Geo Gg = G;
+    if (!G.sr) {  // one global segment: genuine = the whole level
+      Gg.S[0] = Gg.S[1] = Gg.S[2] = 1;
+    }
+    hipLaunchKernelGGL(k_fv_gather, dim3(blocks_for(cells), (unsigned)nseg(G)), dim3(kBlock), 0, s, u,
+                       (const double*)V.u[V.cur], Gg);
+    launched();
+  }
+};
+
+static void release(fv27_plan* P) {
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+  delete P;
+}
+
+static double* dalloc(fv27_plan* P, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(&p, bytes) != hipSuccess) throw hip_error{"hipMalloc failed"};
+  P->allocs.push_back(p);
+  P->bytes += (int64_t)bytes;
+  hipcheck(hipMemset(p, 0, bytes), "hipMemset");
+  return (double*)p;
+}
+
+static void walk_model(fv27_plan* P) {
+  P->launches = 0;
+  P->model_bytes = 0.0;
+  Exec E{P, nullptr, true};
+  E.solve(nullptr, nullptr);
+}
+
+}  // namespace fv
+
+extern "C" {
+
+int32_t fv27_check_params(const fv27_params* p) {
+  const char* m = fv::check(p);
+  return m ? fv::fail(FMG_EINVAL, m) : FMG_OK;
+}
+
+int32_t fv27_plan_create(const fv27_params* p, int32_t device, fv27_plan** out) {
+  if (!out) return fv::fail(FMG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* m = fv::check(p)) return fv::fail(FMG_EINVAL, m);
+  fv27_plan* P = new fv27_plan();
+  P->p = *p;
+  if (p->sr_levels > 0) P->J.assign(p->buffer_schedule, p->buffer_schedule + p->sr_levels);
+  P->p.buffer_schedule = P->J.empty() ? nullptr : P->J.data();
+  P->device = device;
+  P->L = p->levels;
+  P->K = p->sr_levels;
+  P->T = P->L - 1 - P->K;
+  try {
+    fv::hipcheck(hipSetDevice(device), "hipSetDevice");
+    P->lv.resize(P->L);
+    for (int l = 0; l < P->L; ++l) {
+      fv::Level& V = P->lv[l];
+      const int sh = P->L - 1 - l;
+      int n[3] = {p->n[0] >> sh, p->n[1] >> sh, p->n[2] >> sh};
+      V.h = p->h * (double)(1ll << sh);
+      V.G = (l > P->T) ? fv::seg_geo(n, p->segments, P->J[P->L - 1 - l]) : fv::global_geo(n);
+      const size_t cells = (size_t)V.G.box * fv::nseg(V.G);
+      V.u[0] = fv::dalloc(P, cells * sizeof(double));
+      V.u[1] = fv::dalloc(P, cells * sizeof(double));
+      V.rhs = fv::dalloc(P, cells * sizeof(double));
+      V.t = fv::dalloc(P, cells * sizeof(double));
+      V.r = fv::dalloc(P, cells * sizeof(double));
+      if (l < P->L - 1) V.f = fv::dalloc(P, (size_t)n[0] * n[1] * n[2] * sizeof(double));
+    }
+    int n0[3] = {p->n[0] >> (P->L - 1), p->n[1] >> (P->L - 1), p->n[2] >> (P->L - 1)};
+    P->m0 = n0[0] * n0[1] * n0[2];
+    std::vector<double> inv = fv::coarse_inverse(n0, P->lv[0].h);
+    P->Ainv = fv::dalloc(P, inv.size() * sizeof(double));
+    fv::hipcheck(hipMemcpy(P->Ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice),
+                 "hipMemcpy");
+    fv::walk_model(P);
+  } catch (const fv::hip_error& e) {
+    fv::release(P);
+    return fv::fail(e.what.find("hipMalloc") != std::string::npos ? FMG_ENOMEM : FMG_EHIP, e.what);
+  }
+  *out = P;
+  return FMG_OK;
+}
+
+int32_t fv27_plan_execute(fv27_plan* P, const double* f, double* u, void* stream) {
+  if (!P) return fv::fail(FMG_EINVAL, "plan is NULL");
+  if (!f || !u) return fv::fail(FMG_EINVAL, "f or u is NULL");
+  const size_t bytes = sizeof(double) * (size_t)P->p.n[0] * P->p.n[1] * P->p.n[2];
+  const char* fa = (const char*)f;
+  const char* ua = (const char*)u;
+  if (fa < ua + bytes && ua < fa + bytes) return fv::fail(FMG_EINVAL, "f and u overlap");
+  try {
+    fv::hipcheck(hipSetDevice(P->device), "hipSetDevice");
+    fv::Exec E{P, (hipStream_t)stream, false};
+    const int64_t l0 = P->launches;
+    const double b0 = P->model_bytes;
+    E.solve(f, u);
+    P->launches = l0;
+    P->model_bytes = b0;
+  } catch (const fv::hip_error& e) {
+    return fv::fail(FMG_EHIP, e.what);
+  }
+  return FMG_OK;
+}
+
+int32_t fv27_plan_destroy(fv27_plan* P) {
+  if (!P) return FMG_OK;
+  (void)hipSetDevice(P->device);
+  (void)hipDeviceSynchronize();
+  fv::release(P);
+  return FMG_OK;
+}
+
+int64_t fv27_plan_workspace_bytes(const fv27_plan* P) { return P ? P->bytes : 0; }
+
+int32_t fv27_plan_model(const fv27_plan* P, int64_t* launches, double* bytes) {
+  if (!P) return fv::fail(FMG_EINVAL, "plan is NULL");
+  if (launches) *launches = P->launches;
+  if (bytes) *bytes = P->model_bytes;
+  return FMG_OK;
+}
+
+static fv::MarchArgs whole_box_march(const int32_t* n, double h) {
+  fv::MarchArgs A;
+  int nn[3] = {n[0], n[1], n[2]};
+  A.G = fv::global_geo(nn);
+  A.inv_h2 = 1.0 / (h * h);
+  A.rhs = nullptr;
+  A.rhs_global = 1;
+  A.c = 0.0;
+  A.tiles_x = (n[0] + fv::kTX - 1) / fv::kTX;
+  A.zchunk = 8;
+  return A;
+}
+
+static hipError_t launch_march(const fv::MarchArgs& A, const int32_t* n, hipStream_t s) {
+  const int tiles_y = (n[1] + fv::kTY - 1) / fv::kTY;
+  const int chunks = (n[2] + A.zchunk - 1) / A.zchunk;
+  hipLaunchKernelGGL(fv::k_fv_march, dim3((unsigned)(A.tiles_x * tiles_y), (unsigned)chunks, 1),
+                     dim3(fv::kThreads), 0, s, A);
+  return hipGetLastError();
+}
+
+static bool bad_box(const int32_t* n, double h) {
+  return !n || n[0] < 1 || n[1] < 1 || n[2] < 1 || !(h > 0.0) ||
+         (long long)n[0] * n[1] * n[2] > (1ll << 31);
+}
+
+int32_t fv27_op_apply(const double* u, const int32_t* n, double h, double* out, void* stream) {
+  if (!u || !out || bad_box(n, h) || u == out) return fv::fail(FMG_EINVAL, "bad arguments");
+  fv::MarchArgs A = whole_box_march(n, h);
+  A.u = u;
+  A.out = out;
+  A.mode = 2;
+  hipError_t e = launch_march(A, n, (hipStream_t)stream);
+  return e == hipSuccess ? FMG_OK : fv::fail(FMG_EHIP, hipGetErrorString(e));
+}
+
+int32_t fv27_op_cheb(double* u, const double* rhs, const int32_t* n, double h, int32_t degree,
+                     void* stream) {
+  if (!u || !rhs || bad_box(n, h) || degree < 0 || degree > 8 || (const double*)u == rhs)
+    return fv::fail(FMG_EINVAL, "bad arguments");
+  const size_t bytes = sizeof(double) * (size_t)n[0] * n[1] * n[2];
+  hipStream_t s = (hipStream_t)stream;
+  double* tmp = nullptr;
+  if (hipMalloc(&tmp, bytes) != hipSuccess) return fv::fail(FMG_ENOMEM, "hipMalloc failed");
+  fv::MarchArgs A = whole_box_march(n, h);
+  A.rhs = rhs;
+  A.mode = 0;
+  const double d = (121.0 / 24.0) / (h * h);
+  double* cur = u;
+  double* oth = tmp;
+  hipError_t e = hipSuccess;
+  for (int j = 1; j <= degree && e == hipSuccess; ++j) {
+    A.u = cur;
+    A.out = oth;
+    A.c = 1.0 / (d * fv::cheb_root(j, degree));
+    e = launch_march(A, n, s);
+    std::swap(cur, oth);
+  }
+  if (e == hipSuccess && cur != u) e = hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  return e == hipSuccess ? FMG_OK : fv::fail(FMG_EHIP, hipGetErrorString(e));
+}
+
+int32_t fv27_op_prolong(const double* coarse, const int32_t* n, double* fine, void* stream) {
+  if (!coarse || !fine || bad_box(n, 1.0) || (long long)n[0] * n[1] * n[2] > (1ll << 27))
+    return fv::fail(FMG_EINVAL, "bad arguments");
+  int nc[3] = {n[0], n[1], n[2]}, nf[3] = {2 * n[0], 2 * n[1], 2 * n[2]};
+  fv::ProlongArgs A;
+  A.F = fv::global_geo(nf);
+  A.C = fv::global_geo(nc);
+  A.csrc_seg = 0;
+  A.w = coarse;
+  A.t = nullptr;
+  A.u0 = fine;
+  A.u1 = fine;
+  A.add = 0;
+  hipLaunchKernelGGL(fv::k_fv_prolong, dim3(fv::blocks_for(A.F.box), 1), dim3(fv::kBlock), 0,
+                     (hipStream_t)stream, A);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FMG_OK : fv::fail(FMG_EHIP, hipGetErrorString(e));
+}
+
+const char* fv27_last_error(void) { return fv::g_err.c_str(); }
+
+}  // extern "C"

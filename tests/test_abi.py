@@ -1,6 +1,6 @@
 """The C interface on the host (no GPU needed): the library loads, exports
-every function that include/fmg.h declares, and validates parameters before
-any device call."""
+every function that include/fmg.h and include/fv27.h declare, and validates
+parameters before any device call."""
 import ctypes
 import os
 import re
@@ -8,19 +8,20 @@ import re
 import pytest
 
 from paper_1406_7808_amd import fmg
+from paper_1406_7808_amd import fv27
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "fmg.h")).read()
+def _declared(header="fmg.h", prefix="fmg_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fmg_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(%s[a-z_0-9]+)\s*\(" % prefix, src)))
 
 
 def test_every_declared_symbol_is_exported():
-    names = _declared()
-    assert "fmg_plan_execute" in names and len(names) >= 10
+    names = _declared() + _declared("fv27.h", "fv27_")
+    assert "fmg_plan_execute" in names and "fv27_plan_execute" in names and len(names) >= 20
     lib = ctypes.CDLL(fmg._SO)
     for n in names:
         assert hasattr(lib, n), n
@@ -28,6 +29,33 @@ def test_every_declared_symbol_is_exported():
 
 def test_binding_covers_the_header():
     assert sorted(fmg.SYMBOLS) == _declared()
+    assert sorted(fv27.SYMBOLS) == _declared("fv27.h", "fv27_")
+
+
+FV = dict(n=(32, 16, 16), h=1 / 16, levels=5, sr_levels=2, segments=(4, 2, 2), buffers=(2, 2))
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(h=0.0), "h must be positive"),
+    (dict(n=(30, 16, 16)), "divisible by 2^(levels-1)"),
+    (dict(levels=2), "at most 512 cells"),
+    (dict(buffers=(3, 2)), "even"),
+    (dict(buffers=(8, 2)), "at least half"),
+    (dict(segments=(2, 2, 2)), "cubic"),
+    (dict(sr_levels=4, buffers=(2, 2, 2, 2)), "divisible by segments"),
+    (dict(sr_levels=5), "sr_levels"),
+    (dict(degrees=(9, 2, 1)), "Chebyshev degrees"),
+])
+def test_fv27_invalid_parameters_are_rejected(kw, frag):
+    base = dict(FV)
+    base.update(kw)
+    st, msg = fv27.check_params(**base)
+    assert st == fmg.FMG_EINVAL and frag in msg, msg
+
+
+def test_fv27_valid_parameters():
+    assert fv27.check_params(**FV)[0] == 0
+    assert fv27.check_params(**dict(FV, sr_levels=0, buffers=()))[0] == 0
 
 
 def _chk(N, **kw):
