@@ -226,6 +226,18 @@ int32_t fmg_residual_norms(const double *f, const double *u, int32_t N, double *
                            void *stream);
 int32_t fmg_diff_norms(const double *u, const double *v, int32_t N, double *out, void *stream);
 
+/* fmg_residual_norms for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, but the partial sums live in a static device array of
+ * 1024 pairs of doubles (16 KiB per GPU, held until the process ends), out is
+ * a DEVICE array of 2 doubles, and the call only enqueues two kernels on
+ * `stream`: no allocation, no copy, no synchronization.  Any N in 1..4096 fits
+ * (the reduction strides over the grid); larger N is FMG_EINVAL.  Calls that
+ * overlap on one GPU (other streams or threads) share the array and race;
+ * serialize them.  FMG_EINVAL for null pointers or f == u; FMG_EHIP. */
+int32_t fmg_residual_norms_noalloc(const double *f, const double *u, int32_t N, double *out,
+                                   void *stream);
+
 
 /*
  * Batches of independent solves (sizes, parameters and tunings may differ).

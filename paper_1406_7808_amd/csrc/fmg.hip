@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <set>
 #include <stdexcept>
@@ -1598,6 +1599,49 @@ int32_t fmg_residual_norms(const double* f, const double* u, int32_t N, double* 
 
 int32_t fmg_diff_norms(const double* u, const double* v, int32_t N, double* out, void* stream) {
   return norms(u, v, N, 1, out, stream);
+}
+
+// The allocation-free residual norms: the partial pairs live in `scratch`, a
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes the array's name to a kernel: it is a host-side
+// stand-in.  The device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and is kept in scratch_dev.
+constexpr int kScratchPairs = kNormMaxBlocks;
+constexpr int kScratchMaxN = 4096;  // 4096^3 doubles already exceed one GPU's HBM
+static __device__ __align__(256) double scratch[2 * kScratchPairs];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;  // index: device ordinal
+
+static hipError_t scratch_dev(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+int32_t fmg_residual_norms_noalloc(const double* f, const double* u, int32_t N, double* out,
+                                   void* stream) {
+  if (!f || !u || !out || N < 1) return fail(FMG_EINVAL, "bad arguments");
+  if (N > kScratchMaxN) return fail(FMG_EINVAL, "N exceeds 4096, the limit of the static scratch");
+  if (f == u) return fail(FMG_EINVAL, "f and u must not be the same array");
+  const long long nb = norm_blocks(N);
+  if (nb > kScratchPairs)
+    return fail(FMG_EINVAL, "the reduction needs more partials than the static scratch holds");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FMG_EHIP, "hipGetDevice failed");
+  double* part = nullptr;
+  hipError_t e = scratch_dev(dev, &part);
+  if (e != hipSuccess) return fail(FMG_EHIP, hipGetErrorString(e));
+  // every partial pair the final reduction reads is written by this call's
+  // first kernel, so nothing needs clearing
+  e = norms_launch(f, u, N, 0, part, out, (hipStream_t)stream);
+  return e == hipSuccess ? FMG_OK : fail(FMG_EHIP, hipGetErrorString(e));
 }
 
 int32_t fmg_op_apply(const double* u, int32_t n, double* out, void* stream) {

@@ -62,7 +62,8 @@ SYMBOLS = ["fmg_check_params", "fmg_plan_create", "fmg_plan_execute", "fmg_plan_
            "fmg_plan_profile_read", "fmg_schedule_model", "fmg_batch_create", "fmg_batch_execute",
            "fmg_batch_capture", "fmg_batch_replay", "fmg_batch_workspace_bytes",
            "fmg_batch_destroy", "fmg_last_error", "fmg_residual_norms", "fmg_diff_norms",
-           "fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict", "fmg_op_interp"]
+           "fmg_residual_norms_noalloc", "fmg_op_apply", "fmg_op_smooth", "fmg_op_restrict",
+           "fmg_op_interp"]
 
 
 def lib():
@@ -120,11 +121,13 @@ def lib():
     dp = ctypes.POINTER(ctypes.c_double)
     L.fmg_residual_norms.argtypes = [vp, vp, i32, dp, vp]
     L.fmg_diff_norms.argtypes = [vp, vp, i32, dp, vp]
+    L.fmg_residual_norms_noalloc.argtypes = [vp, vp, i32, vp, vp]
     L.fmg_op_apply.argtypes = [vp, i32, vp, vp]
     L.fmg_op_smooth.argtypes = [vp, vp, i32, i32, vp]
     L.fmg_op_restrict.argtypes = [vp, i32, vp, vp]
     L.fmg_op_interp.argtypes = [vp, i32, vp, vp]
-    for name in ("fmg_residual_norms", "fmg_diff_norms", "fmg_op_apply", "fmg_op_smooth",
+    for name in ("fmg_residual_norms", "fmg_diff_norms", "fmg_residual_norms_noalloc",
+                 "fmg_op_apply", "fmg_op_smooth",
                  "fmg_op_restrict", "fmg_op_interp"):
         getattr(L, name).restype = i32
     _lib = L
@@ -357,6 +360,18 @@ def residual_norms(f, u, stream=None):
     out = (ctypes.c_double * 2)()
     _check(lib().fmg_residual_norms(_dev(f, N), _dev(u, N), N, out, _stream(stream)))
     return out[0], out[1]
+
+
+def residual_norms_noalloc(f, u, out, stream=None):
+    """The same norms into `out` (a float64 CUDA tensor of 2 entries), with
+    no allocation and no synchronization: only two kernels are enqueued."""
+    N = f.shape[0]
+    if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            and out.numel() >= 2):
+        raise FMGError(FMG_EINVAL, "out must be a contiguous float64 CUDA tensor of 2 entries")
+    _check(lib().fmg_residual_norms_noalloc(_dev(f, N), _dev(u, N), N,
+                                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
 
 
 def diff_norms(u, v, stream=None):
