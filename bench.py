@@ -533,6 +533,8 @@ def main():
                     help="add --variant to profiles/traffic.json from two counter-pass CSVs "
                          "(--steps solves each)")
     ap.add_argument("--commands", default="", help="commands recorded in traffic.json")
+    ap.add_argument("--fv27-only", action="store_true",
+                    help="run only the model-problem leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.traffic_from:
         return traffic_from(args.variant, args.steps, args.traffic_from[0], args.traffic_from[1],
@@ -543,6 +545,9 @@ def main():
         return 2
     if args.counter_pass:
         return counter_pass(args)
+    if args.fv27_only:
+        print(json.dumps(fv27_leg(args)))
+        return 0
 
     import numpy as np
     import torch
