@@ -221,6 +221,8 @@ struct fmg_plan {
   int N = 0, L = 0, K = 0, T = 0, S = 1, n0 = 1, device = 0;
   int nu1 = 2, nu2 = 2, alpha = 1, precision = FMG_FP64, refine = 2;
   bool fused = true;          // temporally blocked smoother (else single-cell kernels)
+  bool zres = true;           // large global levels: the last pre-smoothing pass of two
+                              // half-sweeps also restricts (residual epilogue)
   int Lc = 0;                 // global levels 0..Lc run in the persistent coarse kernel
   int lds_max = 0;            // LDS bytes a workgroup may use (box-resident smoother)
   int max_stages = 4;         // half-sweeps per temporally blocked launch (2 or 4)
@@ -486,7 +488,7 @@ struct Exec {
     // two workgroups per CU (at most 64 VGPRs) where the kernel fits them
     // (not the latency variant: its launches are small)
     constexpr int WPE =
-        (PF == 1 && NS <= 2 && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD && !RES))) ? 8 : 4;
+        (PF == 1 && NS <= 2 && !RES && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD))) ? 8 : 4;
     const Geo& G = H.geo[l];
     if (PRO != PRO_LOAD && (!c || !ct)) throw hip_error("internal: null coarse increment");
     SmoothArgs<T> a{};
@@ -503,8 +505,8 @@ struct Exec {
     if (outmode && (!inpl || !out)) throw hip_error("internal: output epilogue needs an in-place pass");
     a.out = out;
     a.outmode = outmode;
-    if (RES != (rmode >= 0) || (RES && (!inpl || l < 1)))
-      throw hip_error("internal: residual epilogue needs an in-place pass");
+    if (RES != (rmode >= 0) || (RES && (l < 1 || (!inpl && (nseg(l) != 1 || rmode != 0)))))
+      throw hip_error("internal: residual epilogue needs an in-place pass or a global level");
     a.rmode = rmode;
     a.uc = RES ? H.u[l - 1] : nullptr;
     a.rc = RES ? H.rhs[l - 1] : nullptr;
@@ -524,13 +526,16 @@ struct Exec {
       // every stored cell inside the domain is written, so the new copy is whole
       int wext = cext(l) + 2 * G.ghost;
       if (wext > G.n) wext = G.n;
-      constexpr int HH = NS;  // tile halo
+      // tile halo (one more for a residual epilogue, whose restriction also
+      // needs even output extents: coarse cells are not split between tiles)
+      constexpr int HH = NS + RES;
       // tile shape: the fewest loaded columns covering the write region
       long long best = -1;
       // even widths: the kernel deals each row's columns to two colour classes
       for (int tx = 2 * HH + 2; tx <= 256 && tx * (2 * HH + 2) <= NC; tx += 2) {
         int ty = NC / tx;
         if (ty > wext + 2 * HH) ty = wext + 2 * HH;
+        if (RES) ty &= ~1;
         if (ty < 2 * HH + 2) continue;
         long long cost = (long long)((wext + tx - 2 * HH - 1) / (tx - 2 * HH)) *
                          ((wext + ty - 2 * HH - 1) / (ty - 2 * HH)) * tx * ty;
@@ -553,6 +558,7 @@ struct Exec {
       if (ntz > zmax) ntz = zmax;
       if (ntz < 1) ntz = 1;
       a.zc = (wext + ntz - 1) / ntz;
+      if (RES) a.zc += a.zc & 1;  // chunks of whole coarse planes
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
@@ -816,6 +822,11 @@ struct Exec {
       if (pr == PRO_LOAD && rmode >= 0 && inpl && ns == 2 && st == ns && !om) {
         // the last pass of a pre-smoothing also restricts (residual epilogue)
         smooth_z<2, 2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, true, nullptr, 0, rmode);
+        restricted = true;
+      } else if (pr == PRO_LOAD && rmode == 0 && !inpl && nseg(l) == 1 && !cols_level(l) &&
+                 ns == 2 && st == ns && sizeof(T) == 8 && P->zres) {
+        // ... over two copies on a large global level (one more halo column)
+        smooth_z<2, 2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, false, nullptr, 0, 0);
         restricted = true;
       } else if (pr == PRO_LOAD && rmode == 0 && !inpl && cols_level(l) && st == ns) {
         // ... and over two copies on the small global levels

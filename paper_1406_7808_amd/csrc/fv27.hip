@@ -192,6 +192,7 @@ struct MarchArgs {
   double c;
   double inv_h2;
   int tiles_x, zchunk;
+  double* fin;  // the solve's last step: genuine cells also go to the caller's u (or null)
 };
 
 // An xy tile of kTX x kTY columns of one segment's compute region marches a
@@ -249,7 +250,14 @@ __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
         const double f =
             A.rhs_global ? A.rhs[((long long)zc * G.n[1] + y) * G.n[0] + x] : A.rhs[id];
         const double r = f - Lu;
-        A.out[id] = A.mode ? r : c1 - A.c * r;
+        const double v = A.mode ? r : c1 - A.c * r;
+        A.out[id] = v;
+        if (A.fin) {  // the genuine cells of the finest level (every cell of a global one)
+          int vlo[3], vhi[3];
+          seg_genuine(G, q, vlo, vhi);
+          if (x >= vlo[0] && x < vhi[0] && y >= vlo[1] && y < vhi[1] && zc >= vlo[2] && zc < vhi[2])
+            A.fin[((long long)zc * G.n[1] + y) * G.n[0] + x] = v;
+        }
       }
     }
   }
@@ -610,11 +618,13 @@ struct Exec {
 
   // one march pass over level l: mode 0 Chebyshev step (cur -> other), mode 1
   // residual into lv.r
-  void march(int l, const double* rhs, bool rhs_global, int mode, double c) {
+  void march(int l, const double* rhs, bool rhs_global, int mode, double c,
+             double* fin_u = nullptr) {
     Level& V = P->lv[l];
     const Geo& G = V.G;
-    MarchArgs A;
+    MarchArgs A{};
     A.G = G;
+    A.fin = fin_u;
     A.u = V.u[V.cur];
     A.out = mode ? V.r : V.u[V.cur ^ 1];
     A.rhs = rhs;
@@ -635,8 +645,11 @@ struct Exec {
     int chunks = (int)std::max(1ll, std::min((long long)(ext[2] + 7) / 8, (2048 + cols - 1) / cols));
     A.zchunk = (ext[2] + chunks - 1) / chunks;
     chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
-    count(c_cells(G) * 24.0);
-    if (dry) return;
+    count(c_cells(G) * 24.0 + (fin_u ? 8.0 * G.n[0] * G.n[1] * G.n[2] : 0.0));
+    if (dry) {
+      if (mode == 0) V.cur ^= 1;
+      return;
+    }
     hipLaunchKernelGGL(k_fv_march, dim3((unsigned)(A.tiles_x * tiles_y), (unsigned)chunks,
                                         (unsigned)nseg(G)),
                        dim3(kThreads), 0, s, A);
@@ -644,17 +657,25 @@ struct Exec {
     if (mode == 0) V.cur ^= 1;
   }
 
-  void cheb(int l, const double* rhs, bool rhs_global, int degree) {
+  // the caller's u while the solve's last smoothing runs: its last step
+  // writes the genuine cells there too, and no gather is needed
+  double* fin = nullptr;
+  bool fin_done = false;
+
+  void cheb(int l, const double* rhs, bool rhs_global, int degree, bool last = false) {
     Level& V = P->lv[l];
     const double d = (121.0 / 24.0) / (V.h * V.h);
-    for (int j = 1; j <= degree; ++j) march(l, rhs, rhs_global, 0, 1.0 / (d * cheb_root(j, degree)));
+    for (int j = 1; j <= degree; ++j)
+      march(l, rhs, rhs_global, 0, 1.0 / (d * cheb_root(j, degree)),
+            last && j == degree ? fin : nullptr);
+    if (last && degree > 0 && fin) fin_done = true;
   }
 
   // restriction of u (and the residual) from level l into level l-1
   void restrict_level(int l, int target) {
     Level& F = P->lv[l];
     Level& C = P->lv[l - 1];
-    RestrictArgs A;
+    RestrictArgs A{};
     A.F = F.G;
     A.C = C.G;
     A.fu = F.u[F.cur];
@@ -682,7 +703,7 @@ struct Exec {
   void fas(int l) {  // coarse level l - 1 of fine level l
     Level& F = P->lv[l];
     Level& C = P->lv[l - 1];
-    FasArgs A;
+    FasArgs A{};
     A.C = C.G;
     A.F = F.G;
     A.u = C.u[C.cur];
@@ -701,7 +722,7 @@ struct Exec {
   void prolong(int l, int add) {
     Level& F = P->lv[l];
     Level& C = P->lv[l - 1];
-    ProlongArgs A;
+    ProlongArgs A{};
     A.F = F.G;
     A.C = C.G;
     A.csrc_seg = C.G.sr;
@@ -740,7 +761,7 @@ struct Exec {
     fas(l);
     vcycle_global(l - 1, P->lv[l - 1].rhs);
     prolong(l, 1);
-    cheb(l, rhs, true, P->p.cheb_post);
+    cheb(l, rhs, true, P->p.cheb_post, l == P->L - 1);
     (void)V;
   }
 
@@ -762,7 +783,7 @@ struct Exec {
       vcycle_global(l - 1, P->lv[l - 1].rhs);
     }
     prolong(l, 1);
-    cheb(l, rhs, atop, P->p.cheb_post);
+    cheb(l, rhs, atop, P->p.cheb_post, l == P->L - 1);
   }
 
   void f_hierarchy(const double* f) {
@@ -770,7 +791,7 @@ struct Exec {
     for (int l = P->L - 1; l > 0; --l) {
       Level& F = P->lv[l];
       Level& C = P->lv[l - 1];
-      RestrictArgs A;
+      RestrictArgs A{};
       A.F = global_geo(F.G.n);
       A.C = global_geo(C.G.n);
       A.fu = F.f;
@@ -790,6 +811,8 @@ struct Exec {
   void solve(const double* f, double* u) {
     const int L = P->L;
     for (auto& V : P->lv) V.cur = 0;
+    fin = dry ? (double*)(uintptr_t)1 : u;  // (a dry walk only counts)
+    fin_done = false;
     f_hierarchy(f);
     // global FMG stages 0..T (Fig. 2)
     coarse_solve(P->lv[0].f);
@@ -804,7 +827,9 @@ struct Exec {
       cheb(top, P->lv[top].f, true, P->p.cheb_fmg);
       vcycle_sr(top, top);
     }
-    // output: the genuine cells of the finest level
+    // output: the genuine cells of the finest level, unless its last
+    // smoothing step wrote them (no post-smoothing, or a one-level solve)
+    if (fin_done) return;
     Level& V = P->lv[L - 1];
     const Geo& G = V.G;
     const long long cells = G.sr ? (long long)G.g * G.g * G.g : G.box;
@@ -935,7 +960,7 @@ int32_t fv27_plan_model(const fv27_plan* P, int64_t* launches, double* bytes) {
 }
 
 static fv::MarchArgs whole_box_march(const int32_t* n, double h) {
-  fv::MarchArgs A;
+  fv::MarchArgs A{};
   int nn[3] = {n[0], n[1], n[2]};
   A.G = fv::global_geo(nn);
   A.inv_h2 = 1.0 / (h * h);
@@ -944,6 +969,7 @@ static fv::MarchArgs whole_box_march(const int32_t* n, double h) {
   A.c = 0.0;
   A.tiles_x = (n[0] + fv::kTX - 1) / fv::kTX;
   A.zchunk = 8;
+  A.fin = nullptr;  // single operators deliver nothing beyond `out`
   return A;
 }
 
@@ -1002,7 +1028,7 @@ int32_t fv27_op_prolong(const double* coarse, const int32_t* n, double* fine, vo
   if (!coarse || !fine || bad_box(n, 1.0) || (long long)n[0] * n[1] * n[2] > (1ll << 27))
     return fv::fail(FMG_EINVAL, "bad arguments");
   int nc[3] = {n[0], n[1], n[2]}, nf[3] = {2 * n[0], 2 * n[1], 2 * n[2]};
-  fv::ProlongArgs A;
+  fv::ProlongArgs A{};
   A.F = fv::global_geo(nf);
   A.C = fv::global_geo(nc);
   A.csrc_seg = 0;

@@ -108,7 +108,9 @@ k_smooth_z(SmoothArgs<T> a) {
   const Box B = seg_box(gu, q);
   const int n = gu.n;
   const bool inpl = a.inplace != 0;
-  constexpr int H = NS;  // tile halo
+  // tile halo: NS columns; a residual over two copies needs the neighbours of
+  // the output columns final too, one more
+  const int H = NS + ((RES && !inpl) ? 1 : 0);
   const int txw = a.txw, tyw = a.tyw, sx = txw - 2 * H, sy = tyw - 2 * H;
   // blocks are dealt round-robin to the L2 domains: give each domain a
   // contiguous range of tiles so neighbouring tiles share an L2
@@ -149,7 +151,9 @@ k_smooth_z(SmoothArgs<T> a) {
   // The epilogue trails the last plane by two steps (residual, then the
   // coarse cells of the last coarse plane).
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
-  const int p0 = oz - NS, p1 = zs1 - 1 + NS + 2 * RES;
+  // (over two copies the residual epilogue's march starts one plane lower, so
+  // that the plane below the chunk is final for its residual too)
+  const int p0 = oz - NS - ((RES && !inpl) ? 1 : 0), p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box(a.gr, q);
