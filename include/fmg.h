@@ -120,8 +120,10 @@ int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *strea
  *                  segment, 4 half-sweeps per pass (default 1);
  *   box            1: segment levels whose whole storage box fits the LDS of
  *                  one workgroup use the box-resident smoother (default 1);
- *   target_blocks  workgroups a streaming pass aims for, 64..65536
- *                  (default 1024).
+ *   target_blocks  workgroups a streaming pass aims for, 64..65536, or 0
+ *                  (default): on levels above 64^3 the z chunks of each
+ *                  pass over two copies are chosen for the fewest rounds of
+ *                  resident workgroups times chunk depth, elsewhere 1024.
  * fmg_plan_set_tuning re-plans the schedule on the host (no device call);
  * FMG_EINVAL for out-of-range values.
  */

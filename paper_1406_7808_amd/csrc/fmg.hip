@@ -230,7 +230,8 @@ struct fmg_plan {
   bool use_box = true;        // segment levels whose box fits LDS: box-resident smoother
   std::set<const void*> lds_attr;  // kernels already allowed the whole LDS
   std::vector<double*> ck;         // level checkpoints (empty: none)
-  long long target_blocks = 1024;  // workgroups a fused launch aims for
+  long long target_blocks = 0;  // workgroups a fused launch aims for (0: chosen per pass)
+  int ncu = 256;                // compute units of the device
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
   Hier<double> h64;
@@ -550,15 +551,41 @@ struct Exec {
       a.ntx = (wext + SX - 1) / SX;
       a.nty = (wext + SY - 1) / SY;
       long long bxy = (long long)a.ntx * a.nty * ns;
-      int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
       // large levels keep chunks at least 2 NS deep (recomputed halo planes);
       // small, L2-resident levels split finely to shorten the serial z march
       int zmax = wext <= 64 ? (wext + 1) / 2 : wext / (2 * NS);
       if (zmax < 1) zmax = 1;
-      if (ntz > zmax) ntz = zmax;
-      if (ntz < 1) ntz = 1;
-      a.zc = (wext + ntz - 1) / ntz;
-      if (RES) a.zc += a.zc & 1;  // chunks of whole coarse planes
+      auto chunk = [&](int nz) {  // planes per chunk for nz chunks
+        int zc = (wext + nz - 1) / nz;
+        if (RES) zc += zc & 1;  // chunks of whole coarse planes
+        return zc;
+      };
+      int ntz;
+      if (P->target_blocks == 0 && wext > 64) {
+        // chosen by rounds of resident workgroups: every chunk marches its
+        // planes plus NS (+1) halo planes, and a launch takes as many such
+        // marches as it has rounds of workgroups, the last one too however
+        // few it holds
+        const long long slots = (long long)P->ncu * (WPE / 4);
+        long long bestc = -1;
+        ntz = 1;
+        for (int nz = 1; nz <= zmax; ++nz) {
+          const int zc = chunk(nz);
+          const int nzr = (wext + zc - 1) / zc;
+          const long long rounds = (bxy * nzr + slots - 1) / slots;
+          const long long c = rounds * (zc + 2 * NS + RES);
+          if (bestc < 0 || c < bestc) {  // ties: fewer, longer chunks
+            bestc = c;
+            ntz = nz;
+          }
+        }
+      } else {
+        const long long tb = P->target_blocks ? P->target_blocks : 1024;
+        ntz = (int)((tb + bxy - 1) / bxy);
+        if (ntz > zmax) ntz = zmax;
+        if (ntz < 1) ntz = 1;
+      }
+      a.zc = chunk(ntz);
       a.ntz = (wext + a.zc - 1) / a.zc;
     }
     if (a.txw & 1) throw hip_error("internal: the smoother's tile width must be even");
@@ -952,7 +979,7 @@ struct Exec {
     a.nty = (ce + a.cty - 1) / a.cty;
     int ns = nseg(l);
     long long bxy = (long long)a.ntx * a.nty * ns;
-    int ntz = (int)((P->target_blocks + bxy - 1) / bxy);
+    int ntz = (int)(((P->target_blocks ? P->target_blocks : 1024) + bxy - 1) / bxy);
     // chunks of at least 8 coarse planes: each re-reads two halo fine planes
     int zmax = ce / 8 < 1 ? 1 : ce / 8;
     if (ntz > zmax) ntz = zmax;
@@ -1155,6 +1182,11 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess)
       P->lds_max = v;
+    else
+      (void)hipGetLastError();
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        v > 0)
+      P->ncu = v;
     else
       (void)hipGetLastError();
   }
@@ -1382,8 +1414,8 @@ int32_t fmg_plan_set_tuning(fmg_plan* P, const fmg_tuning* t) {
   if (t->max_stages != 2 && t->max_stages != 4) return fail(FMG_EINVAL, "max_stages must be 2 or 4");
   if ((t->seg_inplace != 0 && t->seg_inplace != 1) || (t->box != 0 && t->box != 1))
     return fail(FMG_EINVAL, "seg_inplace and box must be 0 or 1");
-  if (t->target_blocks < 64 || t->target_blocks > 65536)
-    return fail(FMG_EINVAL, "target_blocks must be in 64..65536");
+  if (t->target_blocks != 0 && (t->target_blocks < 64 || t->target_blocks > 65536))
+    return fail(FMG_EINVAL, "target_blocks must be 0 or in 64..65536");
   P->max_stages = t->max_stages;
   P->seg_inplace = t->seg_inplace != 0;
   P->use_box = t->box != 0;

@@ -341,7 +341,7 @@ class Batch:
             pass
 
 
-DEFAULT_TUNING = {"max_stages": 4, "seg_inplace": 1, "box": 1, "target_blocks": 1024}
+DEFAULT_TUNING = {"max_stages": 4, "seg_inplace": 1, "box": 1, "target_blocks": 0}
 
 
 def solve(f, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",

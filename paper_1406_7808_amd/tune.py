@@ -24,7 +24,7 @@ import torch
 from . import fmg
 
 CANDIDATES = [{"max_stages": ms, "seg_inplace": ip, "box": bx, "target_blocks": tb}
-              for ms, ip, bx, tb in itertools.product((2, 4), (1, 0), (1, 0), (512, 1024, 2048))]
+              for ms, ip, bx, tb in itertools.product((2, 4), (1, 0), (1, 0), (0, 512, 1024, 2048))]
 
 
 def default_cache_path():
