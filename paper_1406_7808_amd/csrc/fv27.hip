@@ -367,42 +367,68 @@ struct ProlongArgs {
 };
 
 // trilinear prolongation onto every storage cell inside the domain (C and
-// the frozen ghosts): the FMG step, or the V-cycle correction
+// the frozen ghosts): the FMG step, or the V-cycle correction.  One thread
+// per coarse parent writes its (up to) 8 children: the 3 x 3 x 3 coarse
+// values they use (w - t, or u; only those a child needs, reflected at the
+// walls) are loaded once.  Each child sums its 8 weighted values in the same
+// order as a child-by-child evaluation.
 __global__ void __launch_bounds__(kBlock) k_fv_prolong(ProlongArgs A) {
   const int q = blockIdx.y;
   const Geo& G = A.F;
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= G.box) return;
   int clo[3], chi[3], slo[3];
   seg_region(G, q, clo, chi, slo);
-  const int x = slo[0] + (int)(t % G.m[0]), y = slo[1] + (int)((t / G.m[0]) % G.m[1]),
-            z = slo[2] + (int)(t / ((long long)G.m[0] * G.m[1]));
-  if (x < 0 || y < 0 || z < 0 || x >= G.n[0] || y >= G.n[1] || z >= G.n[2]) return;
-  if (x > chi[0] || y > chi[1] || z > chi[2]) return;
+  int flo[3], fhi[3], plo[3], pe[3];
+  for (int d = 0; d < 3; ++d) {  // fine cells written: storage inside the domain
+    flo[d] = G.sr ? max(0, clo[d] - 1) : 0;
+    fhi[d] = G.sr ? min(G.n[d], chi[d] + 1) : G.n[d];
+    plo[d] = flo[d] >> 1;
+    pe[d] = ((fhi[d] - 1) >> 1) + 1 - plo[d];
+  }
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)pe[0] * pe[1] * pe[2]) return;
+  const int P[3] = {plo[0] + (int)(t % pe[0]), plo[1] + (int)((t / pe[0]) % pe[1]),
+                    plo[2] + (int)(t / ((long long)pe[0] * pe[1]))};
+  bool v0[3], v1[3];  // child 2P (v0) and 2P + 1 (v1) written, per dimension
+  for (int d = 0; d < 3; ++d) {
+    v0[d] = 2 * P[d] >= flo[d] && 2 * P[d] < fhi[d];
+    v1[d] = 2 * P[d] + 1 >= flo[d] && 2 * P[d] + 1 < fhi[d];
+  }
   const int cq = A.csrc_seg ? q : 0;
   int cclo[3], cchi[3], cslo[3];
   seg_region(A.C, cq, cclo, cchi, cslo);
-  const int fi[3] = {x, y, z};
-  int p[3], o[3];
-  for (int d = 0; d < 3; ++d) {
-    p[d] = fi[d] >> 1;  // fi >= 0
-    o[d] = (fi[d] & 1) ? p[d] + 1 : p[d] - 1;
-  }
-  double s = 0.0;
-  for (int cz = 0; cz < 2; ++cz)
-    for (int cy = 0; cy < 2; ++cy)
-      for (int cx = 0; cx < 2; ++cx) {
-        const double wt = (cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
-        int a = cx ? o[0] : p[0], b = cy ? o[1] : p[1], c = cz ? o[2] : p[2];
-        const double sg = mirror(A.C.n[0], a) * mirror(A.C.n[1], b) * mirror(A.C.n[2], c);
-        const long long cid = sidx(A.C, cq, cslo, a, b, c);
-        const double v = A.add ? A.w[cid] - A.t[cid] : A.w[cid];
-        s += wt * (sg * v);
+  double cv[3][3][3];
+  for (int dz = 0; dz < 3; ++dz)
+    for (int dy = 0; dy < 3; ++dy)
+      for (int dx = 0; dx < 3; ++dx) {
+        const bool need = (dz != 0 || v0[2]) && (dz != 2 || v1[2]) && (dy != 0 || v0[1]) &&
+                          (dy != 2 || v1[1]) && (dx != 0 || v0[0]) && (dx != 2 || v1[0]);
+        double v = 0.0;
+        if (need) {
+          int a = P[0] + dx - 1, b = P[1] + dy - 1, c = P[2] + dz - 1;
+          const double sg = mirror(A.C.n[0], a) * mirror(A.C.n[1], b) * mirror(A.C.n[2], c);
+          const long long cid = sidx(A.C, cq, cslo, a, b, c);
+          v = sg * (A.add ? A.w[cid] - A.t[cid] : A.w[cid]);
+        }
+        cv[dz][dy][dx] = v;
       }
-  const long long id = q * G.box + t;
-  const double nv = A.add ? A.u0[id] + s : s;
-  A.u0[id] = nv;
-  A.u1[id] = nv;
+  for (int kz = 0; kz < 2; ++kz)
+    for (int ky = 0; ky < 2; ++ky)
+      for (int kx = 0; kx < 2; ++kx) {
+        if (!(kz ? v1[2] : v0[2]) || !(ky ? v1[1] : v0[1]) || !(kx ? v1[0] : v0[0])) continue;
+        // the other neighbour of the parent, per dimension: toward the child
+        const int ox = kx ? 2 : 0, oy = ky ? 2 : 0, oz = kz ? 2 : 0;
+        double s = 0.0;
+        for (int cz = 0; cz < 2; ++cz)
+          for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+              const double wt = (cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
+              s += wt * cv[cz ? oz : 1][cy ? oy : 1][cx ? ox : 1];
+            }
+        const long long id = sidx(G, q, slo, 2 * P[0] + kx, 2 * P[1] + ky, 2 * P[2] + kz);
+        const double nv = A.add ? A.u0[id] + s : s;
+        A.u0[id] = nv;
+        A.u1[id] = nv;
+      }
 }
 
 // u = Ainv rhs on the coarsest level (one workgroup)
@@ -465,6 +491,7 @@ struct fv27_plan {
   double* Ainv = nullptr;
   int m0 = 0;
   int64_t bytes = 0;
+  long long march_slots = 256 * 8;  // march workgroups resident at once (CUs x occupancy)
   // schedule model of the last walk
   int64_t launches = 0;
   double model_bytes = 0.0;
@@ -577,6 +604,13 @@ static double cheb_root(int j, int k) {
 
 static unsigned blocks_for(long long cells) { return (unsigned)((cells + kBlock - 1) / kBlock); }
 
+// coarse parents of the fine cells a prolongation writes, at most, per segment
+static long long parents(const Geo& G) {
+  long long c = 1;
+  for (int d = 0; d < 3; ++d) c *= G.sr ? ((G.m[d] + 1) >> 1) + 1 : (G.n[d] + 1) >> 1;
+  return c;
+}
+
 // One solve's launches (or, with dry, only their count and bytes).
 struct Exec {
   fv27_plan* P;
@@ -641,10 +675,21 @@ struct Exec {
     A.tiles_x = (ext[0] + kTX - 1) / kTX;
     const int tiles_y = (ext[1] + kTY - 1) / kTY;
     const long long cols = (long long)A.tiles_x * tiles_y * nseg(G);
-    // enough workgroups to fill the chip, chunks of at least 8 planes
-    int chunks = (int)std::max(1ll, std::min((long long)(ext[2] + 7) / 8, (2048 + cols - 1) / cols));
-    A.zchunk = (ext[2] + chunks - 1) / chunks;
-    chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
+    // z chunks: the fewest rounds of resident workgroups times the planes a
+    // chunk marches (its own plus two halo planes), the last round counted
+    // whole; ties to fewer, longer chunks
+    long long bestc = -1;
+    A.zchunk = ext[2];
+    for (int nz = 1; nz <= ext[2]; ++nz) {
+      const int zc = (ext[2] + nz - 1) / nz;
+      const long long blocks = cols * ((ext[2] + zc - 1) / zc);
+      const long long c = ((blocks + P->march_slots - 1) / P->march_slots) * (zc + 2);
+      if (bestc < 0 || c < bestc) {
+        bestc = c;
+        A.zchunk = zc;
+      }
+    }
+    const int chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
     count(c_cells(G) * 24.0 + (fin_u ? 8.0 * G.n[0] * G.n[1] * G.n[2] : 0.0));
     if (dry) {
       if (mode == 0) V.cur ^= 1;
@@ -734,8 +779,8 @@ struct Exec {
     const double fc = storage_cells(F.G);
     count(fc * (add ? 24.0 : 16.0) + storage_cells(C.G) * (add ? 16.0 : 8.0));
     if (dry) return;
-    hipLaunchKernelGGL(k_fv_prolong, dim3(blocks_for(F.G.box), (unsigned)nseg(F.G)), dim3(kBlock), 0,
-                       s, A);
+    hipLaunchKernelGGL(k_fv_prolong, dim3(blocks_for(parents(F.G)), (unsigned)nseg(F.G)),
+                       dim3(kBlock), 0, s, A);
     launched();
   }
 
@@ -906,6 +951,14 @@ int32_t fv27_plan_create(const fv27_params* p, int32_t device, fv27_plan** out) 
       V.r = fv::dalloc(P, cells * sizeof(double));
       if (l < P->L - 1) V.f = fv::dalloc(P, (size_t)n[0] * n[1] * n[2] * sizeof(double));
     }
+    int ncu = 0, occ = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fv::k_fv_march, fv::kThreads, 0) ==
+            hipSuccess &&
+        ncu > 0 && occ > 0)
+      P->march_slots = (long long)ncu * occ;
+    else
+      (void)hipGetLastError();
     int n0[3] = {p->n[0] >> (P->L - 1), p->n[1] >> (P->L - 1), p->n[2] >> (P->L - 1)};
     P->m0 = n0[0] * n0[1] * n0[2];
     std::vector<double> inv = fv::coarse_inverse(n0, P->lv[0].h);
@@ -1037,8 +1090,8 @@ int32_t fv27_op_prolong(const double* coarse, const int32_t* n, double* fine, vo
   A.u0 = fine;
   A.u1 = fine;
   A.add = 0;
-  hipLaunchKernelGGL(fv::k_fv_prolong, dim3(fv::blocks_for(A.F.box), 1), dim3(fv::kBlock), 0,
-                     (hipStream_t)stream, A);
+  hipLaunchKernelGGL(fv::k_fv_prolong, dim3(fv::blocks_for(fv::parents(A.F)), 1),
+                     dim3(fv::kBlock), 0, (hipStream_t)stream, A);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FMG_OK : fv::fail(FMG_EHIP, hipGetErrorString(e));
 }
