@@ -263,6 +263,162 @@ __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
   }
 }
 
+// Two Chebyshev steps in one pass (temporal blocking): u1 = u - c (rhs - L u)
+// and u2 = u1 - c2 (rhs - L u1) on C.  The tile's planes of u are staged with
+// a 2-cell halo; stage 1 forms u1 on the tile plus a 1-cell halo, one plane
+// behind the load, into a second LDS plane; stage 2 forms u2 on the tile, one
+// plane behind stage 1.  u1 is u itself on the frozen ghosts; beyond a wall
+// stage 2 reads u1 by reflection (mirrored LDS index in x and y, negated P
+// and Q of the wall plane in z), so stage 1 computes only inside the domain.
+constexpr int kT2X = kTX + 2, kT2Y = kTY + 2;          // stage-1 region
+constexpr int kThreads2 = 512;                          // >= kT2X * kT2Y
+static_assert(kT2X * kT2Y <= kThreads2, "stage 1 needs one thread per column");
+
+__global__ void __launch_bounds__(kThreads2) k_fv_march2(MarchArgs A, double c2) {
+  const Geo& G = A.G;
+  const int q = blockIdx.z;
+  int clo[3], chi[3], slo[3];
+  seg_region(G, q, clo, chi, slo);
+  const int tx = blockIdx.x % A.tiles_x, ty = blockIdx.x / A.tiles_x;
+  const int x0 = clo[0] + tx * kTX, y0 = clo[1] + ty * kTY;
+  const int z0 = clo[2] + blockIdx.y * A.zchunk;
+  if (x0 >= chi[0] || y0 >= chi[1] || z0 >= chi[2]) return;  // uniform over the block
+  const int z1 = min(chi[2], z0 + A.zchunk);
+  const int nz = G.n[2];
+
+  __shared__ double U0[2][kTY + 4][kTX + 4];
+  __shared__ double U1[2][kT2Y][kT2X];
+
+  // stage 1: column (c1x, c1y) of the tile plus a 1-cell halo
+  const int tid = threadIdx.x;
+  const bool s1 = tid < kT2X * kT2Y;
+  const int c1x = tid % kT2X, c1y = tid / kT2X;
+  const int x1 = x0 - 1 + c1x, y1 = y0 - 1 + c1y;
+  const bool dom1 = x1 >= 0 && x1 < G.n[0] && y1 >= 0 && y1 < G.n[1];
+  const bool inc1 = x1 >= clo[0] && x1 < chi[0] && y1 >= clo[1] && y1 < chi[1];
+  const bool sto1 = x1 >= clo[0] - 1 && x1 <= chi[0] && y1 >= clo[1] - 1 && y1 <= chi[1];
+  // stage 2: column (c2x, c2y) of the tile; its 3 x 3 neighbours in U1, a
+  // neighbour beyond a wall read at its mirror with the sign -1
+  const bool s2 = tid < kTX * kTY;
+  const int c2x = tid % kTX, c2y = tid / kTX;
+  const int x2 = x0 + c2x, y2 = y0 + c2y;
+  const bool act2 = s2 && x2 < chi[0] && y2 < chi[1];
+  int ix[3], iy[3];
+  double sx[3], sy[3];
+  for (int k = 0; k < 3; ++k) {
+    int gx = x2 + k - 1, gy = y2 + k - 1;
+    sx[k] = mirror(G.n[0], gx);
+    sy[k] = mirror(G.n[1], gy);
+    // (inactive columns may map outside the plane: clamp, they store nothing)
+    ix[k] = min(max(gx - (x0 - 1), 0), kT2X - 1);
+    iy[k] = min(max(gy - (y0 - 1), 0), kT2Y - 1);
+  }
+  // positions more than two cells from C are never needed; those within,
+  // inside the domain, must lie in the box (C and its ghost layer), and those
+  // beyond a wall mirror into C
+  auto loadable = [&](int g, int d) {
+    return g >= clo[d] - 2 && g <= chi[d] + 1 &&
+           (g < 0 || g >= G.n[d] || (g >= clo[d] - 1 && g <= chi[d]));
+  };
+
+  double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0, cA = 0, cB = 0;  // stage 1 window
+  double R0 = 0, R1 = 0, R2 = 0, S0 = 0, S1 = 0, S2 = 0, dA = 0, dB = 0;  // stage 2 window
+  const int nsteps = z1 - z0 + 4;  // u planes z0 - 2 .. z1 + 1
+  for (int s = 0; s < nsteps; ++s) {
+    const int zl = z0 - 2 + s;
+    double(*u0)[kTX + 4] = U0[s & 1];
+    double(*u1)[kT2X] = U1[s & 1];
+    const bool zload = loadable(zl, 2);
+    for (int i = tid; i < (kTX + 4) * (kTY + 4); i += kThreads2) {
+      const int xx = i % (kTX + 4), yy = i / (kTX + 4);
+      const int gx = x0 - 2 + xx, gy = y0 - 2 + yy;
+      double v = 0.0;
+      if (zload && loadable(gx, 0) && loadable(gy, 1)) v = value(A.u, G, q, slo, gx, gy, zl);
+      u0[yy][xx] = v;
+    }
+    __syncthreads();
+    // stage 1: P and Q of plane zl; u1 of plane zl - 1
+    const int zo1 = zl - 1;
+    if (s1) {
+      const int lx = c1x + 1, ly = c1y + 1;
+      const double ctr = u0[ly][lx];
+      const double face = (u0[ly][lx - 1] + u0[ly][lx + 1]) + (u0[ly - 1][lx] + u0[ly + 1][lx]);
+      const double corner =
+          (u0[ly - 1][lx - 1] + u0[ly - 1][lx + 1]) + (u0[ly + 1][lx - 1] + u0[ly + 1][lx + 1]);
+      P0 = P1;
+      P1 = P2;
+      P2 = -4.0 * kW0 * ctr + (kW0 - 2.0 * kW1) * face + 2.0 * kW1 * corner;
+      Q0 = Q1;
+      Q1 = Q2;
+      Q2 = kW0 * kW0 * ctr + kW0 * kW1 * face + kW1 * kW1 * corner;
+      cA = cB;
+      cB = ctr;
+      if (s >= 2 && zo1 >= 0 && zo1 < nz) {
+        double v = 0.0;
+        const bool inz = zo1 >= clo[2] && zo1 < chi[2];
+        if (dom1 && inc1 && inz) {
+          const double Lu = (kW1 * (P0 + P2) + kW0 * P1 + (Q0 + Q2) - 2.0 * Q1) * A.inv_h2;
+          const double f = A.rhs_global ? A.rhs[((long long)zo1 * G.n[1] + y1) * G.n[0] + x1]
+                                         : A.rhs[sidx(G, q, slo, x1, y1, zo1)];
+          v = cA - A.c * (f - Lu);
+        } else if (dom1 && sto1 && zo1 >= clo[2] - 1 && zo1 <= chi[2]) {
+          v = cA;  // a frozen ghost: u1 = u
+        }
+        u1[c1y][c1x] = v;
+      }
+    }
+    __syncthreads();
+    // stage 2: P and Q of u1's plane zo1 (its mirror beyond a z wall); u2 of
+    // plane zo1 - 1
+    if (s >= 2 && zo1 >= -1 && zo1 <= nz && s2) {
+      double Pn, Qn, ctr = 0.0;
+      if (zo1 >= 0 && zo1 < nz) {
+        double a[3][3];
+        for (int b = 0; b < 3; ++b)
+          for (int e = 0; e < 3; ++e) a[b][e] = sx[e] * sy[b] * u1[iy[b]][ix[e]];
+        ctr = a[1][1];
+        const double face = (a[1][0] + a[1][2]) + (a[0][1] + a[2][1]);
+        const double corner = (a[0][0] + a[0][2]) + (a[2][0] + a[2][2]);
+        Pn = -4.0 * kW0 * ctr + (kW0 - 2.0 * kW1) * face + 2.0 * kW1 * corner;
+        Qn = kW0 * kW0 * ctr + kW0 * kW1 * face + kW1 * kW1 * corner;
+      } else {  // plane -1 or nz: minus its mirror (0 or nz - 1)
+        Pn = -R2;
+        Qn = -S2;
+      }
+      if (zo1 >= -1 && !(zo1 == -1)) {
+        R0 = R1;
+        R1 = R2;
+        R2 = Pn;
+        S0 = S1;
+        S1 = S2;
+        S2 = Qn;
+        dA = dB;
+        dB = ctr;
+        if (zo1 == 0) {  // the plane below the domain mirrors plane 0
+          R1 = -R2;
+          S1 = -S2;
+        }
+      }
+      const int zo2 = zo1 - 1;
+      if (act2 && zo2 >= z0 && zo2 < z1) {
+        const double Lu = (kW1 * (R0 + R2) + kW0 * R1 + (S0 + S2) - 2.0 * S1) * A.inv_h2;
+        const long long id = sidx(G, q, slo, x2, y2, zo2);
+        const double f =
+            A.rhs_global ? A.rhs[((long long)zo2 * G.n[1] + y2) * G.n[0] + x2] : A.rhs[id];
+        const double v = dA - c2 * (f - Lu);
+        A.out[id] = v;
+        if (A.fin) {
+          int vlo[3], vhi[3];
+          seg_genuine(G, q, vlo, vhi);
+          if (x2 >= vlo[0] && x2 < vhi[0] && y2 >= vlo[1] && y2 < vhi[1] && zo2 >= vlo[2] &&
+              zo2 < vhi[2])
+            A.fin[((long long)zo2 * G.n[1] + y2) * G.n[0] + x2] = v;
+        }
+      }
+    }
+  }
+}
+
 // mean of the 8 children of coarse cell (I,J,K) of fine storage v
 __device__ inline double mean8(const double* v, const Geo& F, int q, const int slo[3], int I,
                                int J, int K) {
@@ -491,7 +647,8 @@ struct fv27_plan {
   double* Ainv = nullptr;
   int m0 = 0;
   int64_t bytes = 0;
-  long long march_slots = 256 * 8;  // march workgroups resident at once (CUs x occupancy)
+  long long march_slots = 256 * 8;   // march workgroups resident at once (CUs x occupancy)
+  long long march2_slots = 256 * 4;  // ... of the two-step march
   // schedule model of the last walk
   int64_t launches = 0;
   double model_bytes = 0.0;
@@ -674,21 +831,7 @@ struct Exec {
     }
     A.tiles_x = (ext[0] + kTX - 1) / kTX;
     const int tiles_y = (ext[1] + kTY - 1) / kTY;
-    const long long cols = (long long)A.tiles_x * tiles_y * nseg(G);
-    // z chunks: the fewest rounds of resident workgroups times the planes a
-    // chunk marches (its own plus two halo planes), the last round counted
-    // whole; ties to fewer, longer chunks
-    long long bestc = -1;
-    A.zchunk = ext[2];
-    for (int nz = 1; nz <= ext[2]; ++nz) {
-      const int zc = (ext[2] + nz - 1) / nz;
-      const long long blocks = cols * ((ext[2] + zc - 1) / zc);
-      const long long c = ((blocks + P->march_slots - 1) / P->march_slots) * (zc + 2);
-      if (bestc < 0 || c < bestc) {
-        bestc = c;
-        A.zchunk = zc;
-      }
-    }
+    A.zchunk = zchunk_for(ext[2], (long long)A.tiles_x * tiles_y * nseg(G), P->march_slots, 2);
     const int chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
     count(c_cells(G) * 24.0 + (fin_u ? 8.0 * G.n[0] * G.n[1] * G.n[2] : 0.0));
     if (dry) {
@@ -702,17 +845,81 @@ struct Exec {
     if (mode == 0) V.cur ^= 1;
   }
 
+  // z chunks of a march over `ext` planes with `cols` tile columns: the fewest
+  // rounds of resident workgroups times the planes a chunk marches (its own
+  // plus `halo`), the last round counted whole; ties to fewer, longer chunks
+  static int zchunk_for(int ext, long long cols, long long slots, int halo) {
+    long long bestc = -1;
+    int best = ext;
+    for (int nz = 1; nz <= ext; ++nz) {
+      const int zc = (ext + nz - 1) / nz;
+      const long long blocks = cols * ((ext + zc - 1) / zc);
+      const long long c = ((blocks + slots - 1) / slots) * (zc + halo);
+      if (bestc < 0 || c < bestc) {
+        bestc = c;
+        best = zc;
+      }
+    }
+    return best;
+  }
+
+  // two Chebyshev steps (coefficients c and c2) in one temporally blocked
+  // pass over level l (cur -> other)
+  void march2(int l, const double* rhs, bool rhs_global, double c, double c2,
+              double* fin_u = nullptr) {
+    Level& V = P->lv[l];
+    const Geo& G = V.G;
+    MarchArgs A{};
+    A.G = G;
+    A.fin = fin_u;
+    A.u = V.u[V.cur];
+    A.out = V.u[V.cur ^ 1];
+    A.rhs = rhs;
+    A.rhs_global = rhs_global ? 1 : 0;
+    A.mode = 0;
+    A.c = c;
+    A.inv_h2 = 1.0 / (V.h * V.h);
+    int ext[3];
+    for (int d = 0; d < 3; ++d) ext[d] = G.sr ? std::min(G.n[d], G.g + 2 * G.J) : G.n[d];
+    A.tiles_x = (ext[0] + kTX - 1) / kTX;
+    const int tiles_y = (ext[1] + kTY - 1) / kTY;
+    A.zchunk = zchunk_for(ext[2], (long long)A.tiles_x * tiles_y * nseg(G), P->march2_slots, 4);
+    const int chunks = (ext[2] + A.zchunk - 1) / A.zchunk;
+    count(c_cells(G) * 24.0 + (fin_u ? 8.0 * G.n[0] * G.n[1] * G.n[2] : 0.0));
+    V.cur ^= 1;
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_march2, dim3((unsigned)(A.tiles_x * tiles_y), (unsigned)chunks,
+                                         (unsigned)nseg(G)),
+                       dim3(kThreads2), 0, s, A, c2);
+    launched();
+  }
+
   // the caller's u while the solve's last smoothing runs: its last step
   // writes the genuine cells there too, and no gather is needed
   double* fin = nullptr;
   bool fin_done = false;
+  bool fused2 = true;  // two Chebyshev steps per pass
 
   void cheb(int l, const double* rhs, bool rhs_global, int degree, bool last = false) {
     Level& V = P->lv[l];
     const double d = (121.0 / 24.0) / (V.h * V.h);
-    for (int j = 1; j <= degree; ++j)
-      march(l, rhs, rhs_global, 0, 1.0 / (d * cheb_root(j, degree)),
-            last && j == degree ? fin : nullptr);
+    // steps in pairs, each pair one temporally blocked pass
+    // (the two-step pass reads two cells beyond a wall: every extent >= 2).
+    // Segment levels keep one step per pass: their compute regions give the
+    // two-step pass (512 threads per workgroup) too few workgroups to hide
+    // its per-plane latency, and it measured slower there.
+    const bool two = fused2 && !V.G.sr && V.G.n[0] >= 2 && V.G.n[1] >= 2 && V.G.n[2] >= 2;
+    for (int j = 1; j <= degree;) {
+      double* fo = last && (j == degree || (two && j + 1 == degree)) ? fin : nullptr;
+      if (two && j + 1 <= degree) {
+        march2(l, rhs, rhs_global, 1.0 / (d * cheb_root(j, degree)),
+               1.0 / (d * cheb_root(j + 1, degree)), fo);
+        j += 2;
+      } else {
+        march(l, rhs, rhs_global, 0, 1.0 / (d * cheb_root(j, degree)), fo);
+        j += 1;
+      }
+    }
     if (last && degree > 0 && fin) fin_done = true;
   }
 
@@ -959,6 +1166,14 @@ int32_t fv27_plan_create(const fv27_params* p, int32_t device, fv27_plan** out) 
       P->march_slots = (long long)ncu * occ;
     else
       (void)hipGetLastError();
+    occ = 0;
+    if (ncu > 0 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fv::k_fv_march2, fv::kThreads2, 0) ==
+            hipSuccess &&
+        occ > 0)
+      P->march2_slots = (long long)ncu * occ;
+    else
+      (void)hipGetLastError();
     int n0[3] = {p->n[0] >> (P->L - 1), p->n[1] >> (P->L - 1), p->n[2] >> (P->L - 1)};
     P->m0 = n0[0] * n0[1] * n0[2];
     std::vector<double> inv = fv::coarse_inverse(n0, P->lv[0].h);
@@ -1064,11 +1279,24 @@ int32_t fv27_op_cheb(double* u, const double* rhs, const int32_t* n, double h, i
   double* cur = u;
   double* oth = tmp;
   hipError_t e = hipSuccess;
-  for (int j = 1; j <= degree && e == hipSuccess; ++j) {
+  // steps in pairs through the two-step pass (every extent >= 2), as the solver does
+  const bool two = n[0] >= 2 && n[1] >= 2 && n[2] >= 2;
+  for (int j = 1; j <= degree && e == hipSuccess;) {
     A.u = cur;
     A.out = oth;
     A.c = 1.0 / (d * fv::cheb_root(j, degree));
-    e = launch_march(A, n, s);
+    if (two && j + 1 <= degree) {
+      const double c2 = 1.0 / (d * fv::cheb_root(j + 1, degree));
+      const int tiles_y = (n[1] + fv::kTY - 1) / fv::kTY;
+      const int chunks = (n[2] + A.zchunk - 1) / A.zchunk;
+      hipLaunchKernelGGL(fv::k_fv_march2, dim3((unsigned)(A.tiles_x * tiles_y), (unsigned)chunks, 1),
+                         dim3(fv::kThreads2), 0, s, A, c2);
+      e = hipGetLastError();
+      j += 2;
+    } else {
+      e = launch_march(A, n, s);
+      j += 1;
+    }
     std::swap(cur, oth);
   }
   if (e == hipSuccess && cur != u) e = hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, s);
