@@ -517,13 +517,14 @@ struct ProlongArgs {
   int csrc_seg;      // 1: the coarse source is the same segment's box; 0: global
   const double* w;   // coarse source (u for the FMG step; w for the correction)
   const double* t;   // coarse t (correction only; null for the FMG step)
-  double* u0;        // fine copies, both written
+  double* u0;        // fine copies: the current one (every cell) and the other (ghosts)
   double* u1;
   int add;           // 0: u = P w; 1: u += P (w - t)
 };
 
 // trilinear prolongation onto every storage cell inside the domain (C and
-// the frozen ghosts): the FMG step, or the V-cycle correction.  One thread
+// the frozen ghosts) of the current copy, and onto the ghosts of the other
+// copy: the FMG step, or the V-cycle correction.  One thread
 // per coarse parent writes its (up to) 8 children: the 3 x 3 x 3 coarse
 // values they use (w - t, or u; only those a child needs, reflected at the
 // walls) are loaded once.  Each child sums its 8 weighted values in the same
@@ -580,10 +581,15 @@ __global__ void __launch_bounds__(kBlock) k_fv_prolong(ProlongArgs A) {
               const double wt = (cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
               s += wt * cv[cz ? oz : 1][cy ? oy : 1][cx ? ox : 1];
             }
-        const long long id = sidx(G, q, slo, 2 * P[0] + kx, 2 * P[1] + ky, 2 * P[2] + kz);
+        const int fx = 2 * P[0] + kx, fy = 2 * P[1] + ky, fz = 2 * P[2] + kz;
+        const long long id = sidx(G, q, slo, fx, fy, fz);
         const double nv = A.add ? A.u0[id] + s : s;
         A.u0[id] = nv;
-        A.u1[id] = nv;
+        // the other copy needs only the ghosts: its compute region is
+        // rewritten by the next smoothing step before it is read
+        if (fx < clo[0] || fx >= chi[0] || fy < clo[1] || fy >= chi[1] || fz < clo[2] ||
+            fz >= chi[2])
+          A.u1[id] = nv;
       }
 }
 
@@ -983,8 +989,8 @@ struct Exec {
     A.u0 = F.u[F.cur];
     A.u1 = F.u[F.cur ^ 1];
     A.add = add;
-    const double fc = storage_cells(F.G);
-    count(fc * (add ? 24.0 : 16.0) + storage_cells(C.G) * (add ? 16.0 : 8.0));
+    const double fc = storage_cells(F.G), gh = fc - c_cells(F.G);
+    count(fc * (add ? 16.0 : 8.0) + gh * 8.0 + storage_cells(C.G) * (add ? 16.0 : 8.0));
     if (dry) return;
     hipLaunchKernelGGL(k_fv_prolong, dim3(blocks_for(parents(F.G)), (unsigned)nseg(F.G)),
                        dim3(kBlock), 0, s, A);
