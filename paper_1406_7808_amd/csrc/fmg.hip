@@ -1127,8 +1127,12 @@ static void execute(fmg_plan* P, const double* f, double* u, hipStream_t s) {
   E.dry = P->virt;
   for (int it = 0; it <= P->refine; ++it) {
     E.lvl = -1;
-    E.run("k_resid64_to32", (it ? 20.0 : 12.0) * cnt, grid_for(cnt, 1), dim3(kBlock),
-          k_resid64_to32, f, (const double*)u, (int)(it > 0), N, P->r32);
+    const int zc = N >= 128 ? 16 : 8;
+    E.run("k_resid64_to32", (it ? 20.0 : 12.0) * cnt,
+          dim3((unsigned)((N + kResTX - 1) / kResTX), (unsigned)((N + kResTY - 1) / kResTY),
+               (unsigned)((N + zc - 1) / zc)),
+          dim3(kResTX * kResTY), k_resid64_to32, f, (const double*)u, (int)(it > 0), N, zc,
+          P->r32);
     E.fmg(P->r32, u, it > 0);
     E.lvl = -1;
     if (P->K == 0)

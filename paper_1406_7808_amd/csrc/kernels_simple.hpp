@@ -292,17 +292,43 @@ __global__ void k_gather(double* __restrict__ out, const T* __restrict__ u, Geo 
 // ---------------------------------------------------------------------------
 // outer loop of the mixed-precision solve (FP64 residual and update)
 
-// r = (float)(f - L_h u), all in FP64; has_u == 0 means u = 0
-__global__ void k_resid64_to32(const double* __restrict__ f, const double* __restrict__ u,
-                               int has_u, int n, float* __restrict__ r) {
-  Geo G = global_geo(n);
-  Box B = seg_box(G, 0);
-  int x, y, z;
-  if (!cell_of((long long)blockIdx.x * blockDim.x + threadIdx.x, n, n, n, x, y, z)) return;
-  long long id = at(G, B, x, y, z);
-  double v = f[id];
-  if (has_u) v -= apply_L<double, double>(u, G, B, x, y, z);
-  r[id] = (float)v;
+// r = (float)(f - L_h u), all in FP64; has_u == 0 means u = 0.  A tile of
+// kResTX x kResTY columns marches a z chunk of zc planes: each thread keeps
+// its column's planes z - 1, z and z + 1 in registers, and its x and y
+// neighbours are the same plane's loads of adjacent lanes and rows, so they
+// come from the cache.  Neighbours are summed in the order of nb_sum.
+constexpr int kResTX = 64, kResTY = 4;
+__global__ void __launch_bounds__(kResTX * kResTY)
+    k_resid64_to32(const double* __restrict__ f, const double* __restrict__ u, int has_u, int n,
+                   int zc, float* __restrict__ r) {
+  const int x = blockIdx.x * kResTX + (int)(threadIdx.x % kResTX);
+  const int y = blockIdx.y * kResTY + (int)(threadIdx.x / kResTX);
+  const int z0 = blockIdx.z * zc, z1 = min(n, z0 + zc);
+  if (x >= n || y >= n) return;  // (no barrier follows)
+  const long long nn = (long long)n * n, col = (long long)y * n + x;
+  if (!has_u) {
+    for (int z = z0; z < z1; ++z) r[z * nn + col] = (float)f[z * nn + col];
+    return;
+  }
+  const double n2 = (double)n * (double)n;
+  double um = z0 > 0 ? u[(z0 - 1) * nn + col] : 0.0;
+  double uc = z0 < n ? u[z0 * nn + col] : 0.0;
+  for (int z = z0; z < z1; ++z) {
+    const long long id = z * nn + col;
+    const double up = z + 1 < n ? u[id + nn] : 0.0;
+    double s = 0.0;
+    int nb = 0;
+    if (x > 0) s += u[id - 1]; else ++nb;
+    if (x < n - 1) s += u[id + 1]; else ++nb;
+    if (y > 0) s += u[id - n]; else ++nb;
+    if (y < n - 1) s += u[id + n]; else ++nb;
+    if (z > 0) s += um; else ++nb;
+    if (z < n - 1) s += up; else ++nb;
+    const double v = f[id];
+    r[id] = (float)(v - (s - (double)(6 + nb) * uc) * n2);
+    um = uc;
+    uc = up;
+  }
 }
 
 // u (+)= e
