@@ -907,9 +907,9 @@ struct Exec {
     a.alpha = P->alpha;
     if (mode == 0 && checkpoints())
       for (int l = 0; l <= top; ++l) a.ck[l] = P->ck[l];
-    size_t shm = sizeof(T) * (size_t)coarse_lds_elems(a.n, top, mode);
+    size_t shm = coarse_layout(a.n, top, mode, a.mm, sizeof(T), a.ou, a.ot, a.orh, a.of, &a.ort,
+                               &a.oai);
     if ((long long)shm + 1024 > P->lds_max) throw hip_error("internal: coarse levels exceed LDS");
-    // the kernel also holds a small static LDS block (level offsets)
     allow_lds((const void*)k_coarse<T>, P->lds_max - 1024);
     run_shm(mode == 0 ? "k_coarse<fmg>" : "k_coarse<vcycle>", bytes, dim3(1),
             dim3(kCoarseThreads), shm, k_coarse<T>, a);
@@ -1218,7 +1218,7 @@ static int32_t build_plan(int32_t N, const fmg_params* p, int device, bool virt,
       int c = P->Lc + 1;
       if (c > P->T || c >= kCoarseMaxLevels || (N >> (P->L - 1 - c)) > 16) break;
       for (int l = 0; l <= c; ++l) nl[l] = N >> (P->L - 1 - l);
-      if (esz * (size_t)coarse_lds_elems(nl, c, 0) + 1024 > (size_t)P->lds_max) break;
+      if (coarse_layout(nl, c, 0, P->n0 * P->n0 * P->n0, esz) + 1024 > (size_t)P->lds_max) break;
       ++P->Lc;
     }
   }

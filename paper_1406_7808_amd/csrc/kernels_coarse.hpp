@@ -19,10 +19,17 @@
 // ((n+2)^3 elements), so a 7-point sum reads its six neighbours without
 // bounds tests (a zero stands for the eliminated Dirichlet ghost; the
 // diagonal 6 + nb carries the boundary).  t, the right-hand sides and f are
-// read point-wise and stored unpadded (n^3, x fastest).  Threads are mapped
-// to the cells of one colour, so every thread of a half-sweep has work and
-// all its loads are issued before its stores.
+// read point-wise and stored unpadded (n^3, x fastest).  The host forms the
+// offsets (coarse_layout); a small coarsest inverse is staged in LDS too.
+//
+// With 16 wavefronts on the 4 SIMDs of one CU, every vector instruction a
+// thread issues costs ~16 cycles of the phase, so the phases keep per-thread
+// index arithmetic small: the power-of-two edges (2, 4, 8, 16) are template
+// constants (no integer division, immediate LDS offsets), each thread's
+// smoother cells and right-hand sides are set up once per call, and the
+// restriction and correction spread their work over all threads.
 #pragma once
+#include <type_traits>
 #include "grid.hpp"
 #include "kernels_simple.hpp"
 
@@ -30,6 +37,7 @@ namespace fmg {
 
 constexpr int kCoarseMaxLevels = 8;
 constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseAinvLds = 32;  // coarsest levels of up to 32 cells keep A^-1 in LDS
 
 template <class T>
 struct CoarseArgs {
@@ -46,6 +54,11 @@ struct CoarseArgs {
   int fas;      // mode 1: form the FAS right-hand side rt + L u and t = u of level top
   int nu1, nu2, alpha;
   double* ck[kCoarseMaxLevels];  // mode 0: level l's solution after its stage (or null)
+  // LDS layout (coarse_layout), in elements of T: padded u, t and the V-cycle
+  // rhs of each level, f (mode 0), the top level's rhs (mode 1); A^-1 at byte
+  // offset oai, or oai = -1 when it is read from global memory
+  int ou[kCoarseMaxLevels], ot[kCoarseMaxLevels], orh[kCoarseMaxLevels], of[kCoarseMaxLevels];
+  int ort, oai;
 };
 
 // elements of a level's padded u
@@ -54,10 +67,73 @@ __host__ __device__ inline int coarse_padded(int n) {
   return p * p * p;
 }
 
+// The LDS layout of k_coarse for levels 0..top with edges n: the u of every
+// level, then t and rhs of the levels below top, f of every level (mode 0),
+// the top level's rhs (mode 1), and the coarsest inverse (mm cells, FP64,
+// 8-byte aligned) when mm <= kCoarseAinvLds.  Offsets go to the arrays given
+// (any may be null); returns the bytes needed for elements of esz bytes.
+inline size_t coarse_layout(const int* n, int top, int mode, int mm, size_t esz, int* ou = nullptr,
+                            int* ot = nullptr, int* orh = nullptr, int* of = nullptr,
+                            int* ort = nullptr, int* oai = nullptr) {
+  int off = 0;
+  for (int l = 0; l <= top; ++l) {
+    if (ou) ou[l] = off;
+    off += coarse_padded(n[l]);
+  }
+  for (int l = 0; l <= top; ++l) {
+    const int c = n[l] * n[l] * n[l];
+    if (ot) ot[l] = 0;
+    if (orh) orh[l] = 0;
+    if (l < top) {
+      if (ot) ot[l] = off;
+      off += c;
+      if (orh) orh[l] = off;
+      off += c;
+    }
+  }
+  for (int l = 0; l <= top; ++l) {
+    if (of) of[l] = 0;
+    if (mode == 0) {
+      if (of) of[l] = off;
+      off += n[l] * n[l] * n[l];
+    }
+  }
+  if (ort) *ort = off;
+  if (mode == 1) off += n[top] * n[top] * n[top];
+  size_t bytes = esz * (size_t)off;
+  if (oai) *oai = -1;
+  if (mm <= kCoarseAinvLds) {
+    bytes = (bytes + 7) & ~(size_t)7;
+    if (oai) *oai = (int)bytes;
+    bytes += sizeof(double) * (size_t)mm * (size_t)mm;
+  }
+  return bytes;
+}
+
 // padded index of cell (x, y, z) of an n^3 level
 __device__ inline int pidx(int n, int x, int y, int z) {
   const int p = n + 2;
   return ((z + 1) * p + (y + 1)) * p + (x + 1);
+}
+
+// f(std::integral_constant<int, E>) with the edge n as a constant E for the
+// power-of-two edges up to 16, E = 0 (edge read at run time) otherwise
+template <class F>
+__device__ inline void by_edge(int n, F&& f) {
+  if (n == 16) f(std::integral_constant<int, 16>());
+  else if (n == 8) f(std::integral_constant<int, 8>());
+  else if (n == 4) f(std::integral_constant<int, 4>());
+  else if (n == 2) f(std::integral_constant<int, 2>());
+  else f(std::integral_constant<int, 0>());
+}
+
+// threadIdx.x hidden from the optimizer: the per-thread setup of a phase
+// depends only on it and on constants, and would otherwise be hoisted out of
+// the loops over levels and held in registers across the whole cycle
+__device__ inline int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // 1 / (6 + nb) for nb = 0..6 boundary faces (constants, no division)
@@ -114,70 +190,104 @@ __device__ inline GsCell<T> gs_cell(int i, int n, int half) {
   return g;
 }
 
-// Gauss-Seidel update of two cells of colour col: loads, then stores
+// Gauss-Seidel update of the cell at padded index p with right-hand side r
 template <class T>
-__device__ inline void gs_pair(T* u, const T* rhs, int P, int P2, T h2, int col,
-                               const GsCell<T>& a, const GsCell<T>& b) {
-  const int pa = a.p + (col ? a.d : 0), ca = a.c + (col ? a.d : 0);
-  const int pb = b.p + (col ? b.d : 0), cb = b.c + (col ? b.d : 0);
-  const T sa = ((u[pa - 1] + u[pa + 1]) + (u[pa - P] + u[pa + P])) + (u[pa - P2] + u[pa + P2]);
-  const T sb = ((u[pb - 1] + u[pb + 1]) + (u[pb - P] + u[pb + P])) + (u[pb - P2] + u[pb + P2]);
-  const T ra = rhs[ca], rb = rhs[cb];
-  if (a.v) u[pa] = (sa - h2 * ra) * (col ? a.inv1 : a.inv0);
-  if (b.v) u[pb] = (sb - h2 * rb) * (col ? b.inv1 : b.inv0);
+__device__ inline T gs_value(const T* u, int p, int P, int P2, T h2, T r, T inv) {
+  const T s = ((u[p - 1] + u[p + 1]) + (u[p - P] + u[p + P])) + (u[p - P2] + u[p + P2]);
+  return (s - h2 * r) * inv;
 }
 
-// nu red-black sweeps in place, red ((x + y + z) even) first; u padded
-template <class T>
-__device__ void blk_gs(T* u, const T* rhs, int n, int nu) {
+// nu red-black sweeps in place, red ((x + y + z) even) first; u padded.  Each
+// thread owns up to two cells per colour; their indices, diagonals and
+// right-hand sides are set up once for the nu sweeps.
+template <class T, int NE>
+__device__ void blk_gs(T* u, const T* rhs, int n_, int nu) {
   if (nu <= 0) return;
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
   const double h = 1.0 / (double)n;
   const T h2 = (T)(h * h);
   const int P = n + 2, P2 = P * P, half = n * n * (n >> 1);
-  const int NT = blockDim.x, t = threadIdx.x;
-  const GsCell<T> a = gs_cell<T>(t, n, half), b = gs_cell<T>(t + NT, n, half);
+  const int t = opaque_tid();
+  const GsCell<T> a = gs_cell<T>(t, n, half);
+  const T ra0 = rhs[a.c], ra1 = rhs[a.c + a.d];
+  if (half <= NT) {  // one cell per colour (uniform branch)
+    for (int it = 0; it < nu; ++it)
+      for (int col = 0; col < 2; ++col) {
+        if (a.v) {
+          const int pa = a.p + (col ? a.d : 0);
+          u[pa] = gs_value(u, pa, P, P2, h2, col ? ra1 : ra0, col ? a.inv1 : a.inv0);
+        }
+        __syncthreads();
+      }
+    return;
+  }
+  const GsCell<T> b = gs_cell<T>(t + NT, n, half);
+  const T rb0 = rhs[b.c], rb1 = rhs[b.c + b.d];
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) {
-      if (a.v) gs_pair(u, rhs, P, P2, h2, col, a, b);
+      if (a.v) {  // loads of both cells before the stores
+        const int pa = a.p + (col ? a.d : 0), pb = b.p + (col ? b.d : 0);
+        const T va = gs_value(u, pa, P, P2, h2, col ? ra1 : ra0, col ? a.inv1 : a.inv0);
+        const T vb = gs_value(u, pb, P, P2, h2, col ? rb1 : rb0, col ? b.inv1 : b.inv0);
+        u[pa] = va;
+        if (b.v) u[pb] = vb;
+      }
       for (int base = 2 * NT; base < half; base += 2 * NT) {  // levels above 4 NT cells
         const GsCell<T> e = gs_cell<T>(base + t, n, half), f = gs_cell<T>(base + t + NT, n, half);
-        if (e.v) gs_pair(u, rhs, P, P2, h2, col, e, f);
+        if (e.v) {
+          const int pe = e.p + (col ? e.d : 0), pf = f.p + (col ? f.d : 0);
+          const T ve = gs_value(u, pe, P, P2, h2, rhs[e.c + (col ? e.d : 0)], col ? e.inv1 : e.inv0);
+          const T vf = gs_value(u, pf, P, P2, h2, rhs[f.c + (col ? f.d : 0)], col ? f.inv1 : f.inv0);
+          u[pe] = ve;
+          if (f.v) u[pf] = vf;
+        }
       }
       __syncthreads();
     }
 }
 
 // uc = R u, rc = R (rhs - L u) on every coarse cell; then t = uc and
-// rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.
-template <class T>
-__device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc) {
+// rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.  Eight
+// consecutive lanes take one coarse cell, one child each, and sum the
+// children across the lanes.
+template <class T, int NE>
+__device__ void blk_descend(const T* u, const T* rhs, int n_, T* uc, T* rc, T* tc) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
   const int nc = n / 2, cc = nc * nc * nc;
   const int P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  Walk3 w(threadIdx.x, blockDim.x, nc, nc, cc);  // (I, J, K) of coarse cell c
-  for (int c = threadIdx.x; c < cc; c += blockDim.x, w.next()) {
-    const int K = w.k, J = w.j, I = w.i;
-    double su = 0.0, sr = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch) {
-      const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
-      const int p = pidx(n, i, j, k);
-      const double v = (double)u[p];
-      const double s = (((double)u[p - 1] + (double)u[p + 1]) +
-                         ((double)u[p - P] + (double)u[p + P])) +
-                       ((double)u[p - P2] + (double)u[p + P2]);
-      const int nb = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
-      su += v;
-      sr += (double)rhs[(k * n + j) * n + i] - (s - (double)(6 + nb) * v) * s2;
+  const int tid = opaque_tid(), ch = tid & 7;
+  const int di = ch & 1, dj = (ch >> 1) & 1, dk = ch >> 2;
+  Walk3 w(tid >> 3, NT >> 3, nc, nc, cc);  // (I, J, K) of coarse cell c
+#pragma unroll 1
+  for (int c = tid >> 3; c < cc; c += NT >> 3, w.next()) {
+    const int i = 2 * w.i + di, j = 2 * w.j + dj, k = 2 * w.k + dk;
+    const int p = pidx(n, i, j, k);
+    const double v = (double)u[p];
+    const double s = (((double)u[p - 1] + (double)u[p + 1]) + ((double)u[p - P] + (double)u[p + P])) +
+                     ((double)u[p - P2] + (double)u[p + P2]);
+    const int nb = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
+    double su = v, sr = (double)rhs[(k * n + j) * n + i] - (s - (double)(6 + nb) * v) * s2;
+    // the eight lanes of c are active together (c is uniform across them)
+    su += __shfl_xor(su, 1);
+    sr += __shfl_xor(sr, 1);
+    su += __shfl_xor(su, 2);
+    sr += __shfl_xor(sr, 2);
+    su += __shfl_xor(su, 4);
+    sr += __shfl_xor(sr, 4);
+    if (ch == 0) {
+      uc[pidx(nc, w.i, w.j, w.k)] = (T)(su / 8.0);
+      rc[c] = (T)(sr / 8.0);
     }
-    uc[pidx(nc, I, J, K)] = (T)(su / 8.0);
-    rc[c] = (T)(sr / 8.0);
   }
   __syncthreads();
   const int Pc = nc + 2, Pc2 = Pc * Pc;
   const double sc2 = (double)nc * (double)nc;
-  Walk3 w2(threadIdx.x, blockDim.x, nc, nc, cc);
-  for (int c = threadIdx.x; c < cc; c += blockDim.x, w2.next()) {
+  Walk3 w2(tid, NT, nc, nc, cc);
+#pragma unroll 1
+  for (int c = tid; c < cc; c += NT, w2.next()) {
     const int K = w2.k, J = w2.j, I = w2.i;
     const int p = pidx(nc, I, J, K);
     const double v = (double)uc[p];
@@ -191,117 +301,126 @@ __device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc
   __syncthreads();
 }
 
-// u += P(w - t): the increment of each coarse cell goes to its 8 children;
+// u += P(w - t): each fine cell adds the increment of its coarse parent;
 // u and w padded, t plain
-template <class T>
-__device__ void blk_correct(T* u, int n, const T* w, const T* t) {
-  const int nc = n / 2, cc = nc * nc * nc;
-  const int P = n + 2, P2 = P * P;
-  Walk3 wk(threadIdx.x, blockDim.x, nc, nc, cc);
-  for (int c = threadIdx.x; c < cc; c += blockDim.x, wk.next()) {
-    const int K = wk.k, J = wk.j, I = wk.i;
-    const T d = w[pidx(nc, I, J, K)] - t[c];
-    const int p = pidx(n, 2 * I, 2 * J, 2 * K);
-    T v[8];
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch) v[ch] = u[p + (ch >> 2) * P2 + ((ch >> 1) & 1) * P + (ch & 1)];
-#pragma unroll
-    for (int ch = 0; ch < 8; ++ch)
-      u[p + (ch >> 2) * P2 + ((ch >> 1) & 1) * P + (ch & 1)] = (T)(v[ch] + d);
+template <class T, int NE>
+__device__ void blk_correct(T* u, int n_, const T* w, const T* t) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
+  const int nc = n / 2, cnt = n * n * n;
+  const int tid = opaque_tid();
+  Walk3 wk(tid, NT, n, n, cnt);
+#pragma unroll 1
+  for (int i = tid; i < cnt; i += NT, wk.next()) {
+    const int x = wk.i, y = wk.j, z = wk.k, X = x >> 1, Y = y >> 1, Z = z >> 1;
+    const T d = w[pidx(nc, X, Y, Z)] - t[(Z * nc + Y) * nc + X];
+    const int p = pidx(n, x, y, z);
+    u[p] = (T)(u[p] + d);
   }
   __syncthreads();
 }
 
 // FMG interpolation Pi (trilinear, odd reflection at the boundary) of the
-// padded coarse c onto the padded fine u
-template <class T>
-__device__ void blk_interp(T* u, int n, const T* c) {
-  const int cnt = n * n * n, nc = n / 2;
-  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x, w.next()) {
-    const int x = w.i, y = w.j, z = w.k;
-    const int f[3] = {x, y, z};
-    int p[3], r[3];
+// padded coarse c onto the padded fine u.  Per axis a fine cell takes 3/4 of
+// its parent's coarse plane and 1/4 of the next one on its side; beyond a
+// wall that one is the parent itself, entering with sign -1.
+template <class T, int NE>
+__device__ void blk_interp(T* u, int n_, const T* c) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
+  const int cnt = n * n * n, nc = n / 2, Pc = nc + 2, Pc2 = Pc * Pc;
+  const T* c0 = c + pidx(nc, 0, 0, 0);
+  const int tid = opaque_tid();
+  Walk3 w(tid, NT, n, n, cnt);
+#pragma unroll 1
+  for (int i = tid; i < cnt; i += NT, w.next()) {
+    const int f[3] = {w.i, w.j, w.k};
+    int near[3], far[3];
+    bool neg[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      p[d] = f[d] >> 1;
-      r[d] = (f[d] & 1) ? p[d] + 1 : p[d] - 1;
+      const int p = f[d] >> 1, r = (f[d] & 1) ? p + 1 : p - 1;
+      neg[d] = r < 0 || r >= nc;
+      near[d] = p;
+      far[d] = neg[d] ? p : r;
     }
     T s = 0;
+#pragma unroll
     for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
       for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
         for (int cx = 0; cx < 2; ++cx) {
-          int id3[3] = {cx ? r[0] : p[0], cy ? r[1] : p[1], cz ? r[2] : p[2]};
-          T w = (T)((cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75));
-          T sign = 1;
-          for (int d = 0; d < 3; ++d) {
-            if (id3[d] < 0) { id3[d] = -1 - id3[d]; sign = -sign; }
-            else if (id3[d] >= nc) { id3[d] = 2 * nc - 1 - id3[d]; sign = -sign; }
-          }
-          s += w * sign * c[pidx(nc, id3[0], id3[1], id3[2])];
+          const T wt = (T)((cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75));
+          const bool ng = (cx && neg[0]) != ((cy && neg[1]) != (cz && neg[2]));
+          const T sign = ng ? (T)-1 : (T)1;
+          const int o = (cz ? far[2] : near[2]) * Pc2 + (cy ? far[1] : near[1]) * Pc +
+                        (cx ? far[0] : near[0]);
+          s += wt * sign * c0[o];
         }
-    u[pidx(n, x, y, z)] = s;
+    u[pidx(n, w.i, w.j, w.k)] = s;
   }
   __syncthreads();
 }
 
-// exact coarsest solve u0 = A^-1 rhs0 (rhs0 plain, u0 padded)
+// exact coarsest solve u0 = A^-1 rhs0 (rhs0 plain, u0 padded); A in LDS or
+// global memory
 template <class T>
-__device__ void blk_coarse_solve(T* u0, const T* rhs0, int n0, const double* Ainv, int mm) {
+__device__ void blk_coarse_solve(T* u0, const T* rhs0, int n0, const double* A, int mm) {
   for (int r = threadIdx.x; r < mm; r += blockDim.x) {
     double s = 0.0;
-    for (int c = 0; c < mm; ++c) s += Ainv[r * mm + c] * (double)rhs0[c];
+    for (int c = 0; c < mm; ++c) s += A[r * mm + c] * (double)rhs0[c];
     const int z = r / (n0 * n0), y = (r - z * n0 * n0) / n0, x = r - (z * n0 + y) * n0;
     u0[pidx(n0, x, y, z)] = (T)s;
   }
   __syncthreads();
 }
 
-// LDS elements k_coarse needs for levels 0..top with the given edges
-__host__ __device__ inline int coarse_lds_elems(const int* n, int top, int mode) {
-  int e = 0;
-  for (int l = 0; l <= top; ++l) {
-    const int c = n[l] * n[l] * n[l];
-    e += coarse_padded(n[l]);  // u
-    if (l < top) e += 2 * c;   // t, r
-    if (mode == 0) e += c;     // f
-  }
-  if (mode == 1) e += n[top] * n[top] * n[top];  // rhs of the top level
-  return e;
+template <class T>
+__device__ void coarse_solve(unsigned char* raw, T* sm, const CoarseArgs<T>& g, int rofs) {
+  if (g.oai >= 0)
+    blk_coarse_solve(sm + g.ou[0], sm + rofs, g.n[0],
+                     reinterpret_cast<const double*>(raw + g.oai), g.mm);
+  else
+    blk_coarse_solve(sm + g.ou[0], sm + rofs, g.n[0], g.Ainv, g.mm);
 }
-
-// Level data live in one LDS array; per-level offsets are kept in LDS too,
-// so every access is an LDS instruction (no pointer tables in scratch).
-struct CoarseOffsets {
-  int u[kCoarseMaxLevels], t[kCoarseMaxLevels], r[kCoarseMaxLevels], f[kCoarseMaxLevels];
-  int rt, uend;
-};
 
 // FAS V-cycle from level top with right-hand side sm + rto, down to the
 // exact coarsest solve and back up
 template <class T>
-__device__ void blk_vcycle(T* sm, const CoarseOffsets& o, const CoarseArgs<T>& g, int top,
-                           int rto) {
+__device__ void blk_vcycle(unsigned char* raw, T* sm, const CoarseArgs<T>& g, int top, int rto) {
   for (int l = top; l >= 1; --l) {
-    T* rhs = sm + ((l == top) ? rto : o.r[l]);
-    blk_gs(sm + o.u[l], rhs, g.n[l], g.nu1);
-    blk_descend(sm + o.u[l], rhs, g.n[l], sm + o.u[l - 1], sm + o.r[l - 1], sm + o.t[l - 1]);
+    T* rhs = sm + ((l == top) ? rto : g.orh[l]);
+    T* ul = sm + g.ou[l];
+    by_edge(g.n[l], [&](auto E) {
+      constexpr int NE = decltype(E)::value;
+      blk_gs<T, NE>(ul, rhs, g.n[l], g.nu1);
+      blk_descend<T, NE>(ul, rhs, g.n[l], sm + g.ou[l - 1], sm + g.orh[l - 1], sm + g.ot[l - 1]);
+    });
   }
-  blk_coarse_solve(sm + o.u[0], sm + (top == 0 ? rto : o.r[0]), g.n[0], g.Ainv, g.mm);
+  coarse_solve(raw, sm, g, top == 0 ? rto : g.orh[0]);
   for (int l = 1; l <= top; ++l) {
-    T* rhs = sm + ((l == top) ? rto : o.r[l]);
-    blk_correct(sm + o.u[l], g.n[l], sm + o.u[l - 1], sm + o.t[l - 1]);
-    blk_gs(sm + o.u[l], rhs, g.n[l], g.nu2);
+    T* rhs = sm + ((l == top) ? rto : g.orh[l]);
+    T* ul = sm + g.ou[l];
+    by_edge(g.n[l], [&](auto E) {
+      constexpr int NE = decltype(E)::value;
+      blk_correct<T, NE>(ul, g.n[l], sm + g.ou[l - 1], sm + g.ot[l - 1]);
+      blk_gs<T, NE>(ul, rhs, g.n[l], g.nu2);
+    });
   }
 }
 
 // FAS right-hand side of the top level in LDS: r += L u (Eq. 2, in FP64) on
 // every cell, and t = u to global memory; u padded, r plain
-template <class T>
-__device__ void blk_fas_rhs(const T* u, T* r, T* t, int n) {
+template <class T, int NE>
+__device__ void blk_fas_rhs(const T* u, T* r, T* t, int n_) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
   const int cnt = n * n * n, P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
-  for (int c = threadIdx.x; c < cnt; c += blockDim.x, w.next()) {
+  Walk3 w(threadIdx.x, NT, n, n, cnt);
+#pragma unroll 1
+  for (int c = threadIdx.x; c < cnt; c += NT, w.next()) {
     const int x = w.i, y = w.j, z = w.k;
     const int p = pidx(n, x, y, z);
     const double v = (double)u[p];
@@ -314,42 +433,23 @@ __device__ void blk_fas_rhs(const T* u, T* r, T* t, int n) {
   __syncthreads();
 }
 
-// copy an n^3 level between global memory (plain) and LDS (padded or plain);
-// up to four loads per thread are in flight before the stores
-template <class T, bool IN, bool PAD>
-__device__ void blk_copy(T* lds, T* glob, int n) {
-  const int cnt = n * n * n, NT = blockDim.x;
+// The first phase: loads of the top level's data (mode 0: f; mode 1: rhs and
+// u) are issued first; while they are in flight the halos are zeroed (every
+// padded u below the top level whole, the top level's halo cell by cell)
+// and a small A^-1 is staged; then the loaded values are stored.
+template <class T, int NE>
+__device__ void blk_start(unsigned char* raw, T* sm, const CoarseArgs<T>& g) {
+  constexpr int NT = kCoarseThreads;
+  const int top = g.top, n = NE ? NE : g.n[top], cnt = n * n * n;
+  const int P = n + 2;
+  const bool m1 = g.mode == 1;
+  const T* src = m1 ? g.rt : g.f[top];
+  T* dst = sm + (m1 ? g.ort : g.of[top]);
+  T* ut = sm + g.ou[top];
+  const T* gu = g.u[top];
   Walk3 w(threadIdx.x, NT, n, n, cnt);
   for (int base = 0; base < cnt; base += 4 * NT) {
-    T v[4];
-    int li[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = base + threadIdx.x + k * NT;
-      const bool in = i < cnt;
-      li[k] = !in ? 0 : PAD ? pidx(n, w.i, w.j, w.k) : i;
-      w.next();
-      v[k] = in ? (IN ? glob[i] : lds[li[k]]) : (T)0;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = base + threadIdx.x + k * NT;
-      if (i < cnt) {
-        if (IN) lds[li[k]] = v[k];
-        else glob[i] = v[k];
-      }
-    }
-  }
-}
-
-// the right-hand side (plain) and u (padded) of an n^3 level from global
-// memory into LDS, all loads of both issued before the stores
-template <class T>
-__device__ void blk_load_rhs_u(T* lr, const T* gr, T* lu, const T* gu, int n) {
-  const int cnt = n * n * n, NT = blockDim.x;
-  Walk3 w(threadIdx.x, NT, n, n, cnt);
-  for (int base = 0; base < cnt; base += 4 * NT) {
-    T vr[4], vu[4];
+    T v1[4], v2[4];
     int li[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -357,30 +457,73 @@ __device__ void blk_load_rhs_u(T* lr, const T* gr, T* lu, const T* gu, int n) {
       const bool in = i < cnt;
       li[k] = in ? pidx(n, w.i, w.j, w.k) : 0;
       w.next();
-      vr[k] = in ? gr[i] : (T)0;
-      vu[k] = in ? gu[i] : (T)0;
+      v1[k] = in ? src[i] : (T)0;
+      v2[k] = (in && m1) ? gu[i] : (T)0;
+    }
+    if (base == 0) {
+#pragma unroll 1
+      for (int i = threadIdx.x; i < g.ou[top]; i += NT) sm[i] = (T)0;
+      // top halo: the planes z = 0 and z = P - 1, then rows y = 0 and
+      // y = P - 1 of the inner planes, then cells x = 0 and x = P - 1 of the
+      // inner rows
+      const int H1 = 2 * P * P, H2 = H1 + 2 * n * P, H3 = H2 + 2 * n * n;
+#pragma unroll 1
+      for (int k = threadIdx.x; k < H3; k += NT) {
+        int e;
+        if (k < H1) {
+          e = k < P * P ? k : (P - 1) * P * P + (k - P * P);
+        } else if (k < H2) {
+          const int q = k - H1, z = q / (2 * P), r = q - z * 2 * P;
+          e = ((z + 1) * P + (r < P ? 0 : P - 1)) * P + (r < P ? r : r - P);
+        } else {
+          const int q = k - H2, row = q >> 1, z = row / n, y = row - z * n;
+          e = ((z + 1) * P + (y + 1)) * P + ((q & 1) ? P - 1 : 0);
+        }
+        ut[e] = (T)0;
+      }
+      if (g.oai >= 0) {
+        double* ai = reinterpret_cast<double*>(raw + g.oai);
+        for (int k = threadIdx.x; k < g.mm * g.mm; k += NT) ai[k] = g.Ainv[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int i = base + threadIdx.x + k * NT;
       if (i < cnt) {
-        lr[i] = vr[k];
-        lu[li[k]] = vu[k];
+        dst[i] = v1[k];
+        if (m1) ut[li[k]] = v2[k];
       }
     }
   }
+  __syncthreads();
+}
+
+// the top level's u (padded LDS) back to global memory
+template <class T, int NE>
+__device__ void blk_store_top(const T* lds, T* glob, int n_) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_, cnt = n * n * n;
+  Walk3 w(threadIdx.x, NT, n, n, cnt);
+#pragma unroll 1
+  for (int i = threadIdx.x; i < cnt; i += NT, w.next()) glob[i] = lds[pidx(n, w.i, w.j, w.k)];
 }
 
 // f of level l - 1 = R f of level l (mean of the 8 children, summed in FP64
 // in the order of the global restriction kernel); both plain, in LDS
-template <class T>
-__device__ void blk_restrict_f(const T* f, int n, T* fc) {
+template <class T, int NE>
+__device__ void blk_restrict_f(const T* f, int n_, T* fc) {
+  constexpr int NT = kCoarseThreads;
+  const int n = NE ? NE : n_;
   const int nc = n / 2, cnt = nc * nc * nc;
-  Walk3 w(threadIdx.x, blockDim.x, nc, nc, cnt);
-  for (int c = threadIdx.x; c < cnt; c += blockDim.x, w.next()) {
+  Walk3 w(threadIdx.x, NT, nc, nc, cnt);
+#pragma unroll 1
+  for (int c = threadIdx.x; c < cnt; c += NT, w.next()) {
     double s = 0.0;
+#pragma unroll
     for (int k = 0; k < 2; ++k)
+#pragma unroll
       for (int j = 0; j < 2; ++j)
+#pragma unroll
         for (int i = 0; i < 2; ++i)
           s += (double)f[((2 * w.k + k) * n + (2 * w.j + j)) * n + (2 * w.i + i)];
     fc[c] = (T)(s / 8.0);
@@ -399,59 +542,37 @@ __device__ void blk_checkpoint(const T* lds, double* out, int n) {
 
 template <class T>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ unsigned char smem_raw[];  // offset 0: no static LDS
   T* sm = reinterpret_cast<T*>(smem_raw);
-  __shared__ CoarseOffsets o;
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int l = 0; l <= g.top; ++l) {
-      o.u[l] = off;
-      off += coarse_padded(g.n[l]);
-    }
-    o.uend = off;
-    for (int l = 0; l <= g.top; ++l) {
-      const int c = g.n[l] * g.n[l] * g.n[l];
-      o.t[l] = o.r[l] = o.f[l] = 0;
-      if (l < g.top) {
-        o.t[l] = off;
-        off += c;
-        o.r[l] = off;
-        off += c;
-      }
-    }
-    if (g.mode == 0) {
-      for (int l = 0; l <= g.top; ++l) {
-        o.f[l] = off;
-        off += g.n[l] * g.n[l] * g.n[l];
-      }
-    }
-    o.rt = off;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < o.uend; i += blockDim.x) sm[i] = (T)0;  // halos
-  __syncthreads();
-  if (g.mode == 0) {  // f of the top level; the coarser ones are restricted here
-    blk_copy<T, true, false>(sm + o.f[g.top], const_cast<T*>(g.f[g.top]), g.n[g.top]);
-  } else {
-    blk_load_rhs_u(sm + o.rt, g.rt, sm + o.u[g.top], g.u[g.top], g.n[g.top]);
-  }
-  __syncthreads();
+  const int top = g.top;
+  by_edge(g.n[top], [&](auto E) { blk_start<T, decltype(E)::value>(smem_raw, sm, g); });
   if (g.mode == 0)
-    for (int l = g.top; l >= 1; --l) blk_restrict_f(sm + o.f[l], g.n[l], sm + o.f[l - 1]);
+    for (int l = top; l >= 1; --l)
+      by_edge(g.n[l], [&](auto E) {
+        blk_restrict_f<T, decltype(E)::value>(sm + g.of[l], g.n[l], sm + g.of[l - 1]);
+      });
   if (g.mode == 1) {
-    if (g.fas) blk_fas_rhs(sm + o.u[g.top], sm + o.rt, g.t[g.top], g.n[g.top]);
-    blk_vcycle(sm, o, g, g.top, o.rt);
+    if (g.fas)
+      by_edge(g.n[top], [&](auto E) {
+        blk_fas_rhs<T, decltype(E)::value>(sm + g.ou[top], sm + g.ort, g.t[top], g.n[top]);
+      });
+    blk_vcycle(smem_raw, sm, g, top, g.ort);
   } else {
-    blk_coarse_solve(sm + o.u[0], sm + o.f[0], g.n[0], g.Ainv, g.mm);
-    if (g.ck[0]) blk_checkpoint(sm + o.u[0], g.ck[0], g.n[0]);
-    for (int l = 1; l <= g.top; ++l) {
-      blk_interp(sm + o.u[l], g.n[l], sm + o.u[l - 1]);
-      blk_gs(sm + o.u[l], sm + o.f[l], g.n[l], g.alpha);
-      blk_vcycle(sm, o, g, l, o.f[l]);
-      if (g.ck[l]) blk_checkpoint(sm + o.u[l], g.ck[l], g.n[l]);
+    coarse_solve(smem_raw, sm, g, g.of[0]);
+    if (g.ck[0]) blk_checkpoint(sm + g.ou[0], g.ck[0], g.n[0]);
+    for (int l = 1; l <= top; ++l) {
+      by_edge(g.n[l], [&](auto E) {
+        constexpr int NE = decltype(E)::value;
+        blk_interp<T, NE>(sm + g.ou[l], g.n[l], sm + g.ou[l - 1]);
+        blk_gs<T, NE>(sm + g.ou[l], sm + g.of[l], g.n[l], g.alpha);
+      });
+      blk_vcycle(smem_raw, sm, g, l, g.of[l]);
+      if (g.ck[l]) blk_checkpoint(sm + g.ou[l], g.ck[l], g.n[l]);
     }
   }
-  blk_copy<T, false, true>(sm + o.u[g.top], g.u[g.top], g.n[g.top]);
+  by_edge(g.n[top], [&](auto E) {
+    blk_store_top<T, decltype(E)::value>(sm + g.ou[top], g.u[top], g.n[top]);
+  });
 }
 
 }  // namespace fmg
