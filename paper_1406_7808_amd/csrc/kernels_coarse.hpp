@@ -24,10 +24,13 @@
 //
 // With 16 wavefronts on the 4 SIMDs of one CU, every vector instruction a
 // thread issues costs ~16 cycles of the phase, so the phases keep per-thread
-// index arithmetic small: the power-of-two edges (2, 4, 8, 16) are template
-// constants (no integer division, immediate LDS offsets), each thread's
-// smoother cells and right-hand sides are set up once per call, and the
-// restriction and correction spread their work over all threads.
+// index arithmetic small: divisions by level extents use the reciprocal
+// (udiv_small), the smoother and the 16^3 correction and FAS right-hand side
+// are also compiled for constant edges (immediate LDS offsets), each
+// thread's smoother cells and right-hand sides are set up once per call, and
+// the restriction and correction spread their work over all threads.  Each
+// operator is inlined once (a single loop over the steps of the cycle), which
+// keeps the kernel's code within reach of the instruction cache.
 #pragma once
 #include <type_traits>
 #include "grid.hpp"
@@ -116,24 +119,61 @@ __device__ inline int pidx(int n, int x, int y, int z) {
   return ((z + 1) * p + (y + 1)) * p + (x + 1);
 }
 
-// f(std::integral_constant<int, E>) with the edge n as a constant E for the
-// power-of-two edges up to 16, E = 0 (edge read at run time) otherwise
-template <class F>
-__device__ inline void by_edge(int n, F&& f) {
-  if (n == 16) f(std::integral_constant<int, 16>());
-  else if (n == 8) f(std::integral_constant<int, 8>());
-  else if (n == 4) f(std::integral_constant<int, 4>());
-  else if (n == 2) f(std::integral_constant<int, 2>());
-  else f(std::integral_constant<int, 0>());
+// floor(a / b) for 0 <= a < 2^22 and 1 <= b < 2^11.  The product with the
+// hardware reciprocal (relative error below 2^-22) lies within one of a / b,
+// so its truncation is the quotient or one off, which one test corrects.
+__device__ inline int udiv_small(int a, int b) {
+  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  const int r = a - q * b;
+  q += r >= b ? 1 : 0;
+  q -= r < 0 ? 1 : 0;
+  return q;
 }
 
+// cell (i, j, k) of an ex x ey x * box walked from linear index c0 in strides
+// of `stride` (the grid-wide Walk3 with the small-operand division)
+struct CWalk {
+  int i, j, k, di, dj, dk, ex, ey;
+  __device__ CWalk(int c0, int stride, int ex_, int ey_) : ex(ex_), ey(ey_) {
+    const int exy = ex * ey;
+    k = udiv_small(c0, exy);
+    const int r = c0 - k * exy;
+    j = udiv_small(r, ex);
+    i = r - j * ex;
+    dk = udiv_small(stride, exy);
+    const int rs = stride - dk * exy;
+    dj = udiv_small(rs, ex);
+    di = rs - dj * ex;
+  }
+  __device__ void next() {
+    i += di;
+    j += dj;
+    k += dk;
+    if (i >= ex) {
+      i -= ex;
+      ++j;
+    }
+    if (j >= ey) {
+      j -= ey;
+      ++k;
+    }
+  }
+};
+
 // threadIdx.x hidden from the optimizer: the per-thread setup of a phase
-// depends only on it and on constants, and would otherwise be hoisted out of
-// the loops over levels and held in registers across the whole cycle
+// depends only on it and on level constants, and would otherwise be hoisted
+// out of the loop over steps and held in registers across the whole cycle
 __device__ inline int opaque_tid() {
   int t = threadIdx.x;
   asm volatile("" : "+v"(t));
   return t;
+}
+
+// the value of lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
+__device__ inline double lane_swap1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
 // 1 / (6 + nb) for nb = 0..6 boundary faces (constants, no division)
@@ -175,9 +215,9 @@ __device__ inline GsCell<T> gs_cell(int i, int n, int half) {
   g.inv0 = g.inv1 = (T)0;
   if (g.v) {
     const int hx = n >> 1;
-    const int rp = i / (2 * hx), w = i - rp * 2 * hx;  // pair of rows, place in it
+    const int rp = udiv_small(i, 2 * hx), w = i - rp * 2 * hx;  // pair of rows, place in it
     const int row = 2 * rp + (w & 1), xh = w >> 1;
-    const int z = row / n, y = row - z * n;
+    const int z = udiv_small(row, n), y = row - z * n;
     const int q = (y + z) & 1;
     const int x0 = 2 * xh + q, x1 = 2 * xh + 1 - q;
     g.p = pidx(n, x0, y, z);
@@ -197,9 +237,11 @@ __device__ inline T gs_value(const T* u, int p, int P, int P2, T h2, T r, T inv)
   return (s - h2 * r) * inv;
 }
 
-// nu red-black sweeps in place, red ((x + y + z) even) first; u padded.  Each
-// thread owns up to two cells per colour; their indices, diagonals and
-// right-hand sides are set up once for the nu sweeps.
+// nu red-black sweeps in place, red ((x + y + z) even) first; u padded.
+// Each thread owns up to two cells per colour (edges up to 16: at most
+// 2 kCoarseThreads cells per colour); their indices, diagonals and
+// right-hand sides are set up once for the nu sweeps.  NE: the edge as a
+// constant (16), or 0.
 template <class T, int NE>
 __device__ void blk_gs(T* u, const T* rhs, int n_, int nu) {
   if (nu <= 0) return;
@@ -209,38 +251,20 @@ __device__ void blk_gs(T* u, const T* rhs, int n_, int nu) {
   const T h2 = (T)(h * h);
   const int P = n + 2, P2 = P * P, half = n * n * (n >> 1);
   const int t = opaque_tid();
-  const GsCell<T> a = gs_cell<T>(t, n, half);
-  const T ra0 = rhs[a.c], ra1 = rhs[a.c + a.d];
-  if (half <= NT) {  // one cell per colour (uniform branch)
-    for (int it = 0; it < nu; ++it)
-      for (int col = 0; col < 2; ++col) {
-        if (a.v) {
-          const int pa = a.p + (col ? a.d : 0);
-          u[pa] = gs_value(u, pa, P, P2, h2, col ? ra1 : ra0, col ? a.inv1 : a.inv0);
-        }
-        __syncthreads();
-      }
-    return;
-  }
-  const GsCell<T> b = gs_cell<T>(t + NT, n, half);
-  const T rb0 = rhs[b.c], rb1 = rhs[b.c + b.d];
+  const GsCell<T> a = gs_cell<T>(t, n, half), b = gs_cell<T>(t + NT, n, half);
+  const T ra0 = rhs[a.c], ra1 = rhs[a.c + a.d], rb0 = rhs[b.c], rb1 = rhs[b.c + b.d];
+  const bool two = half > NT;  // uniform
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) {
       if (a.v) {  // loads of both cells before the stores
         const int pa = a.p + (col ? a.d : 0), pb = b.p + (col ? b.d : 0);
         const T va = gs_value(u, pa, P, P2, h2, col ? ra1 : ra0, col ? a.inv1 : a.inv0);
-        const T vb = gs_value(u, pb, P, P2, h2, col ? rb1 : rb0, col ? b.inv1 : b.inv0);
-        u[pa] = va;
-        if (b.v) u[pb] = vb;
-      }
-      for (int base = 2 * NT; base < half; base += 2 * NT) {  // levels above 4 NT cells
-        const GsCell<T> e = gs_cell<T>(base + t, n, half), f = gs_cell<T>(base + t + NT, n, half);
-        if (e.v) {
-          const int pe = e.p + (col ? e.d : 0), pf = f.p + (col ? f.d : 0);
-          const T ve = gs_value(u, pe, P, P2, h2, rhs[e.c + (col ? e.d : 0)], col ? e.inv1 : e.inv0);
-          const T vf = gs_value(u, pf, P, P2, h2, rhs[f.c + (col ? f.d : 0)], col ? f.inv1 : f.inv0);
-          u[pe] = ve;
-          if (f.v) u[pf] = vf;
+        if (two) {
+          const T vb = gs_value(u, pb, P, P2, h2, col ? rb1 : rb0, col ? b.inv1 : b.inv0);
+          u[pa] = va;
+          if (b.v) u[pb] = vb;
+        } else {
+          u[pa] = va;
         }
       }
       __syncthreads();
@@ -248,36 +272,56 @@ __device__ void blk_gs(T* u, const T* rhs, int n_, int nu) {
 }
 
 // uc = R u, rc = R (rhs - L u) on every coarse cell; then t = uc and
-// rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.  Eight
-// consecutive lanes take one coarse cell, one child each, and sum the
-// children across the lanes.
-template <class T, int NE>
-__device__ void blk_descend(const T* u, const T* rhs, int n_, T* uc, T* rc, T* tc) {
+// rc = rc + L_H uc (FAS right-hand side, Eq. 4).  u, uc padded.  Two
+// neighbouring lanes take one coarse cell: each the four children of one of
+// its two fine planes, reading the 2 x 2 block and its 16 face neighbours
+// once; the two halves are added across the lane pair.
+template <class T>
+__device__ void blk_descend(const T* u, const T* rhs, int n, T* uc, T* rc, T* tc) {
   constexpr int NT = kCoarseThreads;
-  const int n = NE ? NE : n_;
   const int nc = n / 2, cc = nc * nc * nc;
   const int P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  const int tid = opaque_tid(), ch = tid & 7;
-  const int di = ch & 1, dj = (ch >> 1) & 1, dk = ch >> 2;
-  Walk3 w(tid >> 3, NT >> 3, nc, nc, cc);  // (I, J, K) of coarse cell c
+  const int tid = opaque_tid(), hz = tid & 1;
+  CWalk w(tid >> 1, NT >> 1, nc, nc);  // (I, J, K) of coarse cell c
 #pragma unroll 1
-  for (int c = tid >> 3; c < cc; c += NT >> 3, w.next()) {
-    const int i = 2 * w.i + di, j = 2 * w.j + dj, k = 2 * w.k + dk;
-    const int p = pidx(n, i, j, k);
-    const double v = (double)u[p];
-    const double s = (((double)u[p - 1] + (double)u[p + 1]) + ((double)u[p - P] + (double)u[p + P])) +
-                     ((double)u[p - P2] + (double)u[p + P2]);
-    const int nb = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
-    double su = v, sr = (double)rhs[(k * n + j) * n + i] - (s - (double)(6 + nb) * v) * s2;
-    // the eight lanes of c are active together (c is uniform across them)
-    su += __shfl_xor(su, 1);
-    sr += __shfl_xor(sr, 1);
-    su += __shfl_xor(su, 2);
-    sr += __shfl_xor(sr, 2);
-    su += __shfl_xor(su, 4);
-    sr += __shfl_xor(sr, 4);
-    if (ch == 0) {
+  for (int c = tid >> 1; c < cc; c += NT >> 1, w.next()) {
+    const int x0 = 2 * w.i, y0 = 2 * w.j, z = 2 * w.k + hz;
+    const int p = pidx(n, x0, y0, z);  // child (0, 0) of this plane
+    double b[2][2], xm[2], xp[2], ym[2], yp[2], zm[2][2], zp[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        b[j][i] = (double)u[p + j * P + i];
+        zm[j][i] = (double)u[p + j * P + i - P2];
+        zp[j][i] = (double)u[p + j * P + i + P2];
+      }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      xm[q] = (double)u[p + q * P - 1];
+      xp[q] = (double)u[p + q * P + 2];
+      ym[q] = (double)u[p + q - P];
+      yp[q] = (double)u[p + q + 2 * P];
+    }
+    const int nz = (z == 0) + (z == n - 1);
+    double su = 0.0, sr = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int x = x0 + i, y = y0 + j;
+        const double v = b[j][i];
+        const double s = ((i ? b[j][0] : xm[j]) + (i ? xp[j] : b[j][1])) +
+                         ((j ? b[0][i] : ym[i]) + (j ? yp[i] : b[1][i])) + (zm[j][i] + zp[j][i]);
+        const int nb = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1) + nz;
+        su += v;
+        sr += (double)rhs[(z * n + y) * n + x] - (s - (double)(6 + nb) * v) * s2;
+      }
+    // the lane pair of c is active together (c is the same for both)
+    su += lane_swap1(su);
+    sr += lane_swap1(sr);
+    if (hz == 0) {
       uc[pidx(nc, w.i, w.j, w.k)] = (T)(su / 8.0);
       rc[c] = (T)(sr / 8.0);
     }
@@ -285,7 +329,7 @@ __device__ void blk_descend(const T* u, const T* rhs, int n_, T* uc, T* rc, T* t
   __syncthreads();
   const int Pc = nc + 2, Pc2 = Pc * Pc;
   const double sc2 = (double)nc * (double)nc;
-  Walk3 w2(tid, NT, nc, nc, cc);
+  CWalk w2(tid, NT, nc, nc);
 #pragma unroll 1
   for (int c = tid; c < cc; c += NT, w2.next()) {
     const int K = w2.k, J = w2.j, I = w2.i;
@@ -309,7 +353,7 @@ __device__ void blk_correct(T* u, int n_, const T* w, const T* t) {
   const int n = NE ? NE : n_;
   const int nc = n / 2, cnt = n * n * n;
   const int tid = opaque_tid();
-  Walk3 wk(tid, NT, n, n, cnt);
+  CWalk wk(tid, NT, n, n);
 #pragma unroll 1
   for (int i = tid; i < cnt; i += NT, wk.next()) {
     const int x = wk.i, y = wk.j, z = wk.k, X = x >> 1, Y = y >> 1, Z = z >> 1;
@@ -324,14 +368,13 @@ __device__ void blk_correct(T* u, int n_, const T* w, const T* t) {
 // padded coarse c onto the padded fine u.  Per axis a fine cell takes 3/4 of
 // its parent's coarse plane and 1/4 of the next one on its side; beyond a
 // wall that one is the parent itself, entering with sign -1.
-template <class T, int NE>
-__device__ void blk_interp(T* u, int n_, const T* c) {
+template <class T>
+__device__ void blk_interp(T* u, int n, const T* c) {
   constexpr int NT = kCoarseThreads;
-  const int n = NE ? NE : n_;
   const int cnt = n * n * n, nc = n / 2, Pc = nc + 2, Pc2 = Pc * Pc;
   const T* c0 = c + pidx(nc, 0, 0, 0);
   const int tid = opaque_tid();
-  Walk3 w(tid, NT, n, n, cnt);
+  CWalk w(tid, NT, n, n);
 #pragma unroll 1
   for (int i = tid; i < cnt; i += NT, w.next()) {
     const int f[3] = {w.i, w.j, w.k};
@@ -369,9 +412,10 @@ template <class T>
 __device__ void blk_coarse_solve(T* u0, const T* rhs0, int n0, const double* A, int mm) {
   for (int r = threadIdx.x; r < mm; r += blockDim.x) {
     double s = 0.0;
+#pragma unroll 8
     for (int c = 0; c < mm; ++c) s += A[r * mm + c] * (double)rhs0[c];
-    const int z = r / (n0 * n0), y = (r - z * n0 * n0) / n0, x = r - (z * n0 + y) * n0;
-    u0[pidx(n0, x, y, z)] = (T)s;
+    const int z = udiv_small(r, n0 * n0), rr = r - z * n0 * n0, y = udiv_small(rr, n0);
+    u0[pidx(n0, rr - y * n0, y, z)] = (T)s;
   }
   __syncthreads();
 }
@@ -385,49 +429,24 @@ __device__ void coarse_solve(unsigned char* raw, T* sm, const CoarseArgs<T>& g, 
     blk_coarse_solve(sm + g.ou[0], sm + rofs, g.n[0], g.Ainv, g.mm);
 }
 
-// FAS V-cycle from level top with right-hand side sm + rto, down to the
-// exact coarsest solve and back up
-template <class T>
-__device__ void blk_vcycle(unsigned char* raw, T* sm, const CoarseArgs<T>& g, int top, int rto) {
-  for (int l = top; l >= 1; --l) {
-    T* rhs = sm + ((l == top) ? rto : g.orh[l]);
-    T* ul = sm + g.ou[l];
-    by_edge(g.n[l], [&](auto E) {
-      constexpr int NE = decltype(E)::value;
-      blk_gs<T, NE>(ul, rhs, g.n[l], g.nu1);
-      blk_descend<T, NE>(ul, rhs, g.n[l], sm + g.ou[l - 1], sm + g.orh[l - 1], sm + g.ot[l - 1]);
-    });
-  }
-  coarse_solve(raw, sm, g, top == 0 ? rto : g.orh[0]);
-  for (int l = 1; l <= top; ++l) {
-    T* rhs = sm + ((l == top) ? rto : g.orh[l]);
-    T* ul = sm + g.ou[l];
-    by_edge(g.n[l], [&](auto E) {
-      constexpr int NE = decltype(E)::value;
-      blk_correct<T, NE>(ul, g.n[l], sm + g.ou[l - 1], sm + g.ot[l - 1]);
-      blk_gs<T, NE>(ul, rhs, g.n[l], g.nu2);
-    });
-  }
-}
-
 // FAS right-hand side of the top level in LDS: r += L u (Eq. 2, in FP64) on
-// every cell, and t = u to global memory; u padded, r plain
+// every cell; u padded, r plain (t = u was stored by the first phase)
 template <class T, int NE>
-__device__ void blk_fas_rhs(const T* u, T* r, T* t, int n_) {
+__device__ void blk_fas_rhs(const T* u, T* r, int n_) {
   constexpr int NT = kCoarseThreads;
   const int n = NE ? NE : n_;
   const int cnt = n * n * n, P = n + 2, P2 = P * P;
   const double s2 = (double)n * (double)n;
-  Walk3 w(threadIdx.x, NT, n, n, cnt);
+  const int tid = opaque_tid();
+  CWalk w(tid, NT, n, n);
 #pragma unroll 1
-  for (int c = threadIdx.x; c < cnt; c += NT, w.next()) {
+  for (int c = tid; c < cnt; c += NT, w.next()) {
     const int x = w.i, y = w.j, z = w.k;
     const int p = pidx(n, x, y, z);
     const double v = (double)u[p];
     const double s = (((double)u[p - 1] + (double)u[p + 1]) + ((double)u[p - P] + (double)u[p + P])) +
                      ((double)u[p - P2] + (double)u[p + P2]);
     const int nb = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1) + (z == 0) + (z == n - 1);
-    t[c] = u[p];
     r[c] = (T)((double)r[c] + (s - (double)(6 + nb) * v) * s2);
   }
   __syncthreads();
@@ -436,24 +455,28 @@ __device__ void blk_fas_rhs(const T* u, T* r, T* t, int n_) {
 // The first phase: loads of the top level's data (mode 0: f; mode 1: rhs and
 // u) are issued first; while they are in flight the halos are zeroed (every
 // padded u below the top level whole, the top level's halo cell by cell)
-// and a small A^-1 is staged; then the loaded values are stored.
-template <class T, int NE>
+// and a small A^-1 is staged; then the loaded values are stored (with fas
+// also t = u of the top level, straight from the loaded registers).
+template <class T>
 __device__ void blk_start(unsigned char* raw, T* sm, const CoarseArgs<T>& g) {
   constexpr int NT = kCoarseThreads;
-  const int top = g.top, n = NE ? NE : g.n[top], cnt = n * n * n;
+  const int top = g.top, n = g.n[top], cnt = n * n * n;
   const int P = n + 2;
-  const bool m1 = g.mode == 1;
+  const bool m1 = g.mode == 1, fas = m1 && g.fas;
   const T* src = m1 ? g.rt : g.f[top];
   T* dst = sm + (m1 ? g.ort : g.of[top]);
   T* ut = sm + g.ou[top];
   const T* gu = g.u[top];
-  Walk3 w(threadIdx.x, NT, n, n, cnt);
+  T* gt = g.t[top];
+  const int tid = opaque_tid();
+  CWalk w(tid, NT, n, n);
+#pragma unroll 1
   for (int base = 0; base < cnt; base += 4 * NT) {
     T v1[4], v2[4];
     int li[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = base + threadIdx.x + k * NT;
+      const int i = base + tid + k * NT;
       const bool in = i < cnt;
       li[k] = in ? pidx(n, w.i, w.j, w.k) : 0;
       w.next();
@@ -462,36 +485,38 @@ __device__ void blk_start(unsigned char* raw, T* sm, const CoarseArgs<T>& g) {
     }
     if (base == 0) {
 #pragma unroll 1
-      for (int i = threadIdx.x; i < g.ou[top]; i += NT) sm[i] = (T)0;
+      for (int i = tid; i < g.ou[top]; i += NT) sm[i] = (T)0;
       // top halo: the planes z = 0 and z = P - 1, then rows y = 0 and
       // y = P - 1 of the inner planes, then cells x = 0 and x = P - 1 of the
       // inner rows
       const int H1 = 2 * P * P, H2 = H1 + 2 * n * P, H3 = H2 + 2 * n * n;
 #pragma unroll 1
-      for (int k = threadIdx.x; k < H3; k += NT) {
+      for (int k = tid; k < H3; k += NT) {
         int e;
         if (k < H1) {
           e = k < P * P ? k : (P - 1) * P * P + (k - P * P);
         } else if (k < H2) {
-          const int q = k - H1, z = q / (2 * P), r = q - z * 2 * P;
+          const int q = k - H1, z = udiv_small(q, 2 * P), r = q - z * 2 * P;
           e = ((z + 1) * P + (r < P ? 0 : P - 1)) * P + (r < P ? r : r - P);
         } else {
-          const int q = k - H2, row = q >> 1, z = row / n, y = row - z * n;
+          const int q = k - H2, row = q >> 1, z = udiv_small(row, n), y = row - z * n;
           e = ((z + 1) * P + (y + 1)) * P + ((q & 1) ? P - 1 : 0);
         }
         ut[e] = (T)0;
       }
       if (g.oai >= 0) {
         double* ai = reinterpret_cast<double*>(raw + g.oai);
-        for (int k = threadIdx.x; k < g.mm * g.mm; k += NT) ai[k] = g.Ainv[k];
+#pragma unroll 1
+        for (int k = tid; k < g.mm * g.mm; k += NT) ai[k] = g.Ainv[k];
       }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = base + threadIdx.x + k * NT;
+      const int i = base + tid + k * NT;
       if (i < cnt) {
         dst[i] = v1[k];
         if (m1) ut[li[k]] = v2[k];
+        if (fas) gt[i] = v2[k];
       }
     }
   }
@@ -499,25 +524,26 @@ __device__ void blk_start(unsigned char* raw, T* sm, const CoarseArgs<T>& g) {
 }
 
 // the top level's u (padded LDS) back to global memory
-template <class T, int NE>
-__device__ void blk_store_top(const T* lds, T* glob, int n_) {
+template <class T>
+__device__ void blk_store_top(const T* lds, T* glob, int n) {
   constexpr int NT = kCoarseThreads;
-  const int n = NE ? NE : n_, cnt = n * n * n;
-  Walk3 w(threadIdx.x, NT, n, n, cnt);
+  const int cnt = n * n * n;
+  const int tid = opaque_tid();
+  CWalk w(tid, NT, n, n);
 #pragma unroll 1
-  for (int i = threadIdx.x; i < cnt; i += NT, w.next()) glob[i] = lds[pidx(n, w.i, w.j, w.k)];
+  for (int i = tid; i < cnt; i += NT, w.next()) glob[i] = lds[pidx(n, w.i, w.j, w.k)];
 }
 
 // f of level l - 1 = R f of level l (mean of the 8 children, summed in FP64
 // in the order of the global restriction kernel); both plain, in LDS
-template <class T, int NE>
-__device__ void blk_restrict_f(const T* f, int n_, T* fc) {
+template <class T>
+__device__ void blk_restrict_f(const T* f, int n, T* fc) {
   constexpr int NT = kCoarseThreads;
-  const int n = NE ? NE : n_;
   const int nc = n / 2, cnt = nc * nc * nc;
-  Walk3 w(threadIdx.x, NT, nc, nc, cnt);
+  const int tid = opaque_tid();
+  CWalk w(tid, NT, nc, nc);
 #pragma unroll 1
-  for (int c = threadIdx.x; c < cnt; c += NT, w.next()) {
+  for (int c = tid; c < cnt; c += NT, w.next()) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
@@ -535,44 +561,66 @@ __device__ void blk_restrict_f(const T* f, int n_, T* fc) {
 template <class T>
 __device__ void blk_checkpoint(const T* lds, double* out, int n) {
   const int cnt = n * n * n;
-  Walk3 w(threadIdx.x, blockDim.x, n, n, cnt);
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x, w.next())
+  const int tid = opaque_tid();
+  CWalk w(tid, kCoarseThreads, n, n);
+#pragma unroll 1
+  for (int i = tid; i < cnt; i += kCoarseThreads, w.next())
     out[i] = (double)lds[pidx(n, w.i, w.j, w.k)];
 }
 
+// The kernel walks one sequence of steps, so that each operator is
+// instantiated once (the code of a cycle is fetched once per launch, and the
+// instruction cache is shared by two CUs).  Stage lt is an FMG stage (mode 0:
+// lt = 1..top) or the V-cycle (mode 1: lt = top); its steps s are
+//   s = -1 (mode 0): Pi onto level lt, then S^alpha with f_lt;
+//   s = 0..lt-1:     S^nu1 on level lt - s, then restriction (descent);
+//   s = lt:          the exact coarsest solve;
+//   s = lt+1..2 lt:  correction of level s - lt, then S^nu2 (ascent).
+// The smoother, whose phases repeat, is also instantiated for edges 16 and 8.
 template <class T>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
   extern __shared__ unsigned char smem_raw[];  // offset 0: no static LDS
   T* sm = reinterpret_cast<T*>(smem_raw);
   const int top = g.top;
-  by_edge(g.n[top], [&](auto E) { blk_start<T, decltype(E)::value>(smem_raw, sm, g); });
-  if (g.mode == 0)
-    for (int l = top; l >= 1; --l)
-      by_edge(g.n[l], [&](auto E) {
-        blk_restrict_f<T, decltype(E)::value>(sm + g.of[l], g.n[l], sm + g.of[l - 1]);
-      });
-  if (g.mode == 1) {
-    if (g.fas)
-      by_edge(g.n[top], [&](auto E) {
-        blk_fas_rhs<T, decltype(E)::value>(sm + g.ou[top], sm + g.ort, g.t[top], g.n[top]);
-      });
-    blk_vcycle(smem_raw, sm, g, top, g.ort);
-  } else {
+  const bool m0 = g.mode == 0;
+  blk_start(smem_raw, sm, g);
+  if (m0) {
+#pragma unroll 1
+    for (int l = top; l >= 1; --l) blk_restrict_f(sm + g.of[l], g.n[l], sm + g.of[l - 1]);
     coarse_solve(smem_raw, sm, g, g.of[0]);
     if (g.ck[0]) blk_checkpoint(sm + g.ou[0], g.ck[0], g.n[0]);
-    for (int l = 1; l <= top; ++l) {
-      by_edge(g.n[l], [&](auto E) {
-        constexpr int NE = decltype(E)::value;
-        blk_interp<T, NE>(sm + g.ou[l], g.n[l], sm + g.ou[l - 1]);
-        blk_gs<T, NE>(sm + g.ou[l], sm + g.of[l], g.n[l], g.alpha);
-      });
-      blk_vcycle(smem_raw, sm, g, l, g.of[l]);
-      if (g.ck[l]) blk_checkpoint(sm + g.ou[l], g.ck[l], g.n[l]);
-    }
+  } else if (g.fas) {
+    if (g.n[top] == 16) blk_fas_rhs<T, 16>(sm + g.ou[top], sm + g.ort, g.n[top]);
+    else blk_fas_rhs<T, 0>(sm + g.ou[top], sm + g.ort, g.n[top]);
   }
-  by_edge(g.n[top], [&](auto E) {
-    blk_store_top<T, decltype(E)::value>(sm + g.ou[top], g.u[top], g.n[top]);
-  });
+#pragma unroll 1
+  for (int lt = m0 ? 1 : top; lt <= top; ++lt) {
+    const int rto = m0 ? g.of[lt] : g.ort;  // rhs of level lt
+#pragma unroll 1
+    for (int s = m0 ? -1 : 0; s <= 2 * lt; ++s) {
+      if (s == lt) {
+        coarse_solve(smem_raw, sm, g, lt == 0 ? rto : g.orh[0]);
+        continue;
+      }
+      const int l = s < 0 ? lt : s < lt ? lt - s : s - lt;
+      const int n = g.n[l];
+      T* ul = sm + g.ou[l];
+      T* rhs = sm + (l == lt ? rto : g.orh[l]);
+      if (s < 0) blk_interp(ul, n, sm + g.ou[l - 1]);
+      if (s > lt) {
+        if (n == 16) blk_correct<T, 16>(ul, n, sm + g.ou[l - 1], sm + g.ot[l - 1]);
+        else blk_correct<T, 0>(ul, n, sm + g.ou[l - 1], sm + g.ot[l - 1]);
+      }
+      const int nu = s < 0 ? g.alpha : s < lt ? g.nu1 : g.nu2;
+      if (n == 16) blk_gs<T, 16>(ul, rhs, n, nu);
+      else if (n == 8) blk_gs<T, 8>(ul, rhs, n, nu);
+      else blk_gs<T, 0>(ul, rhs, n, nu);
+      if (s >= 0 && s < lt)
+        blk_descend(ul, rhs, n, sm + g.ou[l - 1], sm + g.orh[l - 1], sm + g.ot[l - 1]);
+    }
+    if (m0 && g.ck[lt]) blk_checkpoint(sm + g.ou[lt], g.ck[lt], g.n[lt]);
+  }
+  blk_store_top(sm + g.ou[top], g.u[top], g.n[top]);
 }
 
 }  // namespace fmg
