@@ -662,18 +662,29 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   // bytes per lane, 1 KiB per wavefront instruction, no registers), issued
   // first so that the slot setup overlaps it; cells outside the domain are
   // zeroed once it has landed.  Needs 16-byte alignment of the box and its
-  // length.
+  // length.  With an even box edge every row starts 16-byte aligned, and the
+  // copy skips the planes and rows outside the domain (boundary segments):
+  // per plane inside, one contiguous run of the rows inside.
   const long long bytes = (long long)mc * sizeof(T);
   const bool dma = PRO == PRO_LOAD && ((B.base * (long long)sizeof(T)) & 15) == 0 && (bytes & 15) == 0;
   if (dma) {
     const int nw = NT >> 6, wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const char* src = reinterpret_cast<const char*>(ub);
     char* dst = reinterpret_cast<char*>(bu);
-    for (long long ch = wv; ch * 1024 < bytes; ch += nw) {
-      const long long off = ch * 1024 + ln * 16;
-      if (off < bytes)
-        __builtin_amdgcn_global_load_lds(src + off,
-                                         (__attribute__((address_space(3))) void*)(dst + ch * 1024),
+    const bool rows = (m & 1) == 0;
+    const int zl = rows ? max(0, -B.o[2]) : 0, zh = rows ? min(m, n - B.o[2]) : 1;
+    const int yl = rows ? max(0, -B.o[1]) : 0, yh = rows ? min(m, n - B.o[1]) : m;
+    // run of plane z: bytes [(z m + yl) m, (z m + yh) m) * sizeof(T); without
+    // rows, one run: the whole box
+    const long long run = rows ? (long long)(yh - yl) * m * (long long)sizeof(T) : bytes;
+    const int cpr = (int)((run + 1023) >> 10);  // chunks per run
+    const int nch = (zh - zl) * cpr;
+    for (int ch = wv; ch < nch; ch += nw) {
+      const int pz = zl + ch / cpr, c = ch - (ch / cpr) * cpr;
+      const long long o = ((long long)pz * m + yl) * m * (long long)sizeof(T) + (long long)c * 1024;
+      if ((long long)c * 1024 + ln * 16 < run)
+        __builtin_amdgcn_global_load_lds(src + o + ln * 16,
+                                         (__attribute__((address_space(3))) void*)(dst + o),
                                          16, 0, 0);
     }
   }
