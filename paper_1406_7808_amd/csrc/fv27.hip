@@ -198,7 +198,11 @@ struct MarchArgs {
 // An xy tile of kTX x kTY columns of one segment's compute region marches a
 // z chunk.  Each step stages one plane of u (tile + 1-cell halo, ghosts and
 // reflections resolved) in LDS, forms that plane's P and Q, and finishes the
-// plane one below.  Double-buffered planes: one barrier per step.
+// plane one below.  Double-buffered planes: one barrier per step.  Each
+// thread's staged cells keep their column offset and reflection sign from
+// the start, and their values (and the right-hand side of the next output
+// cell) are loaded one step ahead, so the loads of a plane are in flight
+// while the step before it computes.
 __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
   const Geo& G = A.G;
   const int q = blockIdx.z;
@@ -215,18 +219,60 @@ __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
   // halo columns beyond C + 1 are never needed (and lie outside the box)
   const int xh = min(x0 + kTX, chi[0]), yh = min(y0 + kTY, chi[1]);
 
+  // staged cells of this thread: LDS place, storage offset of the column in
+  // plane slo[2], reflection sign in x and y (0: not staged, stores 0)
+  constexpr int kPl = (kTX + 2) * (kTY + 2), kSl = (kPl + kThreads - 1) / kThreads;
+  int sp[kSl];
+  long long so[kSl];
+  double ss[kSl];
+#pragma unroll
+  for (int k = 0; k < kSl; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    sp[k] = i;
+    so[k] = (long long)q * G.box;
+    ss[k] = 0.0;
+    if (i < kPl) {
+      int gx = x0 - 1 + i % (kTX + 2), gy = y0 - 1 + i / (kTX + 2);
+      if (gx <= xh && gy <= yh) {
+        const double sx = mirror(G.n[0], gx), sy = mirror(G.n[1], gy);
+        ss[k] = sx * sy;
+        so[k] += (long long)(gy - slo[1]) * G.m[0] + (gx - slo[0]);
+      }
+    }
+  }
+  const long long pm = (long long)G.m[0] * G.m[1];
+  // values of the staged cells in plane zl
+  auto fetch = [&](int zl, double(&v)[kSl]) {
+    const double sz = mirror(G.n[2], zl);
+    const long long oz = (long long)(zl - slo[2]) * pm;
+#pragma unroll
+    for (int k = 0; k < kSl; ++k) {
+      const double w = A.u[so[k] + oz];
+      v[k] = ss[k] != 0.0 ? (ss[k] * sz) * w : 0.0;
+    }
+  };
+  // right-hand side of this thread's cell in plane zc
+  const bool wants_f = active && A.mode != 2;
+  auto fetch_f = [&](int zc) -> double {
+    return A.rhs_global ? A.rhs[((long long)zc * G.n[1] + y) * G.n[0] + x]
+                        : A.rhs[sidx(G, q, slo, x, y, zc)];
+  };
+
   __shared__ double plane[2][kTY + 2][kTX + 2];
   double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0, c1 = 0, c2 = 0;
   const int nsteps = z1 - z0 + 2;
+  double va[kSl], vb[kSl];
+  double fa = 0.0, fb = 0.0;  // right-hand side of this step's and the next step's output cell
+  fetch(z0 - 1, va);
   for (int s = 0; s < nsteps; ++s) {
     const int zl = z0 - 1 + s;
     double(*pl)[kTX + 2] = plane[s & 1];
-    for (int i = threadIdx.x; i < (kTX + 2) * (kTY + 2); i += kThreads) {
-      const int xx = i % (kTX + 2), yy = i / (kTX + 2);
-      const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
-      double v = 0.0;
-      if (gx <= xh && gy <= yh) v = value(A.u, G, q, slo, gx, gy, zl);
-      pl[yy][xx] = v;
+#pragma unroll
+    for (int k = 0; k < kSl; ++k)
+      if (sp[k] < kPl) (&pl[0][0])[sp[k]] = va[k];
+    if (s + 1 < nsteps) {
+      fetch(zl + 1, vb);
+      if (s >= 1 && wants_f) fb = fetch_f(zl);  // step s + 1 finishes plane zl
     }
     __syncthreads();
     const double ctr = pl[ly + 1][lx + 1];
@@ -247,9 +293,7 @@ __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
       if (A.mode == 2) {
         A.out[id] = Lu;
       } else {
-        const double f =
-            A.rhs_global ? A.rhs[((long long)zc * G.n[1] + y) * G.n[0] + x] : A.rhs[id];
-        const double r = f - Lu;
+        const double r = fa - Lu;
         const double v = A.mode ? r : c1 - A.c * r;
         A.out[id] = v;
         if (A.fin) {  // the genuine cells of the finest level (every cell of a global one)
@@ -260,6 +304,9 @@ __global__ void __launch_bounds__(kThreads) k_fv_march(MarchArgs A) {
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < kSl; ++k) va[k] = vb[k];
+    fa = fb;
   }
 }
 
@@ -321,20 +368,53 @@ __global__ void __launch_bounds__(kThreads2) k_fv_march2(MarchArgs A, double c2)
            (g < 0 || g >= G.n[d] || (g >= clo[d] - 1 && g <= chi[d]));
   };
 
+  // the staged cell of this thread (one per thread: (kTX + 4)(kTY + 4) <=
+  // kThreads2): storage offset of its column in plane slo[2] and reflection
+  // sign in x and y (0: not loaded); values and right-hand sides are loaded
+  // one step ahead, as in k_fv_march
+  static_assert((kTX + 4) * (kTY + 4) <= kThreads2, "one staged cell per thread");
+  const bool st0 = tid < (kTX + 4) * (kTY + 4);
+  long long so = (long long)q * G.box;
+  double ss = 0.0;
+  if (st0) {
+    int gx = x0 - 2 + tid % (kTX + 4), gy = y0 - 2 + tid / (kTX + 4);
+    if (loadable(gx, 0) && loadable(gy, 1)) {
+      const double sgx = mirror(G.n[0], gx), sgy = mirror(G.n[1], gy);
+      ss = sgx * sgy;
+      so += (long long)(gy - slo[1]) * G.m[0] + (gx - slo[0]);
+    }
+  }
+  const long long pm = (long long)G.m[0] * G.m[1];
+  auto fetch = [&](int zl) -> double {
+    if (!loadable(zl, 2)) return 0.0;  // uniform over the block
+    const double sz = mirror(G.n[2], zl);
+    const double w = A.u[so + (long long)(zl - slo[2]) * pm];
+    return ss != 0.0 ? (ss * sz) * w : 0.0;
+  };
+  auto rhs_at = [&](int x, int y, int z) -> double {
+    return A.rhs_global ? A.rhs[((long long)z * G.n[1] + y) * G.n[0] + x]
+                        : A.rhs[sidx(G, q, slo, x, y, z)];
+  };
+  // stage 1 forms u1 of plane zo1 on its column, stage 2 u2 of plane zo2
+  auto f1_wanted = [&](int zo1) {
+    return s1 && zo1 >= 0 && zo1 < nz && dom1 && inc1 && zo1 >= clo[2] && zo1 < chi[2];
+  };
+  auto f2_wanted = [&](int zo2) { return act2 && zo2 >= z0 && zo2 < z1; };
+
   double P0 = 0, P1 = 0, P2 = 0, Q0 = 0, Q1 = 0, Q2 = 0, cA = 0, cB = 0;  // stage 1 window
   double R0 = 0, R1 = 0, R2 = 0, S0 = 0, S1 = 0, S2 = 0, dA = 0, dB = 0;  // stage 2 window
   const int nsteps = z1 - z0 + 4;  // u planes z0 - 2 .. z1 + 1
+  double va = fetch(z0 - 2), vb = 0.0;
+  double f1a = 0.0, f1b = 0.0, f2a = 0.0, f2b = 0.0;  // right-hand sides, this step and the next
   for (int s = 0; s < nsteps; ++s) {
     const int zl = z0 - 2 + s;
     double(*u0)[kTX + 4] = U0[s & 1];
     double(*u1)[kT2X] = U1[s & 1];
-    const bool zload = loadable(zl, 2);
-    for (int i = tid; i < (kTX + 4) * (kTY + 4); i += kThreads2) {
-      const int xx = i % (kTX + 4), yy = i / (kTX + 4);
-      const int gx = x0 - 2 + xx, gy = y0 - 2 + yy;
-      double v = 0.0;
-      if (zload && loadable(gx, 0) && loadable(gy, 1)) v = value(A.u, G, q, slo, gx, gy, zl);
-      u0[yy][xx] = v;
+    if (st0) (&u0[0][0])[tid] = va;
+    if (s + 1 < nsteps) {  // step s + 1: plane zl + 1, stage 1 at zl, stage 2 at zl - 1
+      vb = fetch(zl + 1);
+      if (s + 1 >= 2 && f1_wanted(zl)) f1b = rhs_at(x1, y1, zl);
+      if (s + 1 >= 2 && f2_wanted(zl - 1)) f2b = rhs_at(x2, y2, zl - 1);
     }
     __syncthreads();
     // stage 1: P and Q of plane zl; u1 of plane zl - 1
@@ -358,9 +438,7 @@ __global__ void __launch_bounds__(kThreads2) k_fv_march2(MarchArgs A, double c2)
         const bool inz = zo1 >= clo[2] && zo1 < chi[2];
         if (dom1 && inc1 && inz) {
           const double Lu = (kW1 * (P0 + P2) + kW0 * P1 + (Q0 + Q2) - 2.0 * Q1) * A.inv_h2;
-          const double f = A.rhs_global ? A.rhs[((long long)zo1 * G.n[1] + y1) * G.n[0] + x1]
-                                         : A.rhs[sidx(G, q, slo, x1, y1, zo1)];
-          v = cA - A.c * (f - Lu);
+          v = cA - A.c * (f1a - Lu);
         } else if (dom1 && sto1 && zo1 >= clo[2] - 1 && zo1 <= chi[2]) {
           v = cA;  // a frozen ghost: u1 = u
         }
@@ -403,9 +481,7 @@ __global__ void __launch_bounds__(kThreads2) k_fv_march2(MarchArgs A, double c2)
       if (act2 && zo2 >= z0 && zo2 < z1) {
         const double Lu = (kW1 * (R0 + R2) + kW0 * R1 + (S0 + S2) - 2.0 * S1) * A.inv_h2;
         const long long id = sidx(G, q, slo, x2, y2, zo2);
-        const double f =
-            A.rhs_global ? A.rhs[((long long)zo2 * G.n[1] + y2) * G.n[0] + x2] : A.rhs[id];
-        const double v = dA - c2 * (f - Lu);
+        const double v = dA - c2 * (f2a - Lu);
         A.out[id] = v;
         if (A.fin) {
           int vlo[3], vhi[3];
@@ -416,6 +492,9 @@ __global__ void __launch_bounds__(kThreads2) k_fv_march2(MarchArgs A, double c2)
         }
       }
     }
+    va = vb;
+    f1a = f1b;
+    f2a = f2b;
   }
 }
 
