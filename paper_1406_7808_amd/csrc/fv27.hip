@@ -688,6 +688,262 @@ __global__ void __launch_bounds__(kBlock) k_fv_coarse(const double* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// The coarse global levels in one workgroup.  Below a few thousand cells a
+// level's operators are latency bound, and a launch per operator costs more
+// than the work: k_fv_cycle runs every operator of levels 0..top (each of at
+// most kCycMaxCells cells) in one 1024-thread workgroup on copies of the
+// levels held in LDS, with a barrier between phases.  It performs either
+//   mode 0: the FMG stages 0..top (Fig. 2): f of level top is restricted
+//           down to level 0, u_0 = A^-1 f_0, then per level the trilinear
+//           FMG step, S^cheb_fmg and one FAS V-cycle with rhs f_l, or
+//   mode 1: one FAS V-cycle (Fig. 1) on level top, from its u and rhs.
+// Each operator takes the arithmetic (and summation order) of its per-cell
+// kernel above; Chebyshev steps alternate between two LDS copies of u.  The
+// result, level top's u, goes to both of its global copies.
+// ---------------------------------------------------------------------------
+constexpr int kCycThreads = 1024;
+constexpr int kCycMaxLevels = 8;
+constexpr int kCycMaxCells = 1024;
+constexpr int kCycArrays = 6;  // per level in LDS: u (two copies), rhs, t, r, f
+
+struct CycleArgs {
+  int top, mode;
+  int n[kCycMaxLevels][3];
+  double inv_h2[kCycMaxLevels];
+  // Chebyshev step coefficients c_j = 1 / (d root_j) per level, j = 0..degree-1
+  double cpre[kCycMaxLevels][8], cpost[kCycMaxLevels][8], cfmg[kCycMaxLevels][8];
+  int dpre, dpost, dfmg;
+  const double* Ainv;  // coarsest inverse (m0 x m0, global memory)
+  int m0;
+  const double* src;   // mode 0: f of level top; mode 1: rhs of level top
+  const double* uin;   // mode 1: u of level top
+  double* uout0;       // level top's result, both copies
+  double* uout1;
+  int o[kCycMaxLevels];  // LDS offset (doubles) of level l's kCycArrays arrays
+};
+
+__device__ inline int cyc_cells(const CycleArgs& A, int l) {
+  return A.n[l][0] * A.n[l][1] * A.n[l][2];
+}
+
+// L v at cell (x, y, z) of a level stored plainly in LDS, odd reflection
+// beyond the walls; the grouping of apply_L_direct
+__device__ inline double cyc_L(const double* v, const int n[3], int x, int y, int z,
+                               double inv_h2) {
+  int ix[3], iy[3], iz[3];
+  double sx[3], sy[3], sz[3];
+  for (int k = 0; k < 3; ++k) {
+    ix[k] = x + k - 1;
+    iy[k] = y + k - 1;
+    iz[k] = z + k - 1;
+    sx[k] = mirror(n[0], ix[k]);
+    sy[k] = mirror(n[1], iy[k]);
+    sz[k] = mirror(n[2], iz[k]);
+  }
+  double P[3], Q[3];
+  for (int c = 0; c < 3; ++c) {
+    double a[3][3];
+    for (int b = 0; b < 3; ++b)
+      for (int e = 0; e < 3; ++e)
+        a[b][e] = (sx[e] * sy[b] * sz[c]) * v[(iz[c] * n[1] + iy[b]) * n[0] + ix[e]];
+    const double ctr = a[1][1];
+    const double face = (a[1][0] + a[1][2]) + (a[0][1] + a[2][1]);
+    const double corner = (a[0][0] + a[0][2]) + (a[2][0] + a[2][2]);
+    P[c] = -4.0 * kW0 * ctr + (kW0 - 2.0 * kW1) * face + 2.0 * kW1 * corner;
+    Q[c] = kW0 * kW0 * ctr + kW0 * kW1 * face + kW1 * kW1 * corner;
+  }
+  return (kW1 * (P[0] + P[2]) + kW0 * P[1] + (Q[0] + Q[2]) - 2.0 * Q[1]) * inv_h2;
+}
+
+__device__ inline void cyc_xyz(int i, const int n[3], int& x, int& y, int& z) {
+  x = i % n[0];
+  y = (i / n[0]) % n[1];
+  z = i / (n[0] * n[1]);
+}
+
+// LDS arrays of level l: 0, 1 the copies of u, 2 rhs, 3 t, 4 r, 5 f
+__device__ inline double* cyc_arr(double* sm, const CycleArgs& A, int l, int k) {
+  return sm + A.o[l] + k * cyc_cells(A, l);
+}
+
+// deg Chebyshev steps on level l with right-hand side rhs; cur: bit l is the
+// LDS copy holding u
+__device__ void cyc_cheb(double* sm, const CycleArgs& A, int l, const double* rhs, int deg,
+                         const double* coef, unsigned& cur) {
+  const int cells = cyc_cells(A, l);
+  for (int j = 0; j < deg; ++j) {
+    const int c0 = (cur >> l) & 1;
+    const double* u = cyc_arr(sm, A, l, c0);
+    double* o = cyc_arr(sm, A, l, c0 ^ 1);
+    for (int i = threadIdx.x; i < cells; i += kCycThreads) {
+      int x, y, z;
+      cyc_xyz(i, A.n[l], x, y, z);
+      const double r = rhs[i] - cyc_L(u, A.n[l], x, y, z, A.inv_h2[l]);
+      o[i] = u[i] - coef[j] * r;
+    }
+    cur ^= 1u << l;
+    __syncthreads();
+  }
+}
+
+// r = rhs - L u on level l, then, level l - 1: u = R u, r = R r (mean of the
+// 8 children, in the order of mean8), rhs = r + L u (Eq. 4) and t = u
+__device__ void cyc_descend(double* sm, const CycleArgs& A, int l, const double* rhs,
+                            unsigned& cur) {
+  const int cells = cyc_cells(A, l);
+  const double* u = cyc_arr(sm, A, l, (cur >> l) & 1);
+  double* r = cyc_arr(sm, A, l, 4);
+  for (int i = threadIdx.x; i < cells; i += kCycThreads) {
+    int x, y, z;
+    cyc_xyz(i, A.n[l], x, y, z);
+    r[i] = rhs[i] - cyc_L(u, A.n[l], x, y, z, A.inv_h2[l]);
+  }
+  __syncthreads();
+  const int c = l - 1, cc = cyc_cells(A, c);
+  cur &= ~(1u << c);
+  double* uc = cyc_arr(sm, A, c, 0);
+  double* rc = cyc_arr(sm, A, c, 4);
+  const int* nf = A.n[l];
+  for (int i = threadIdx.x; i < cc; i += kCycThreads) {
+    int I, J, K;
+    cyc_xyz(i, A.n[c], I, J, K);
+    double su = 0.0, sr = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int f = ((2 * K + cz) * nf[1] + (2 * J + b)) * nf[0] + (2 * I + a);
+          su += u[f];
+          sr += r[f];
+        }
+    uc[i] = su / 8.0;
+    rc[i] = sr / 8.0;
+  }
+  __syncthreads();
+  double* rhc = cyc_arr(sm, A, c, 2);
+  double* tc = cyc_arr(sm, A, c, 3);
+  for (int i = threadIdx.x; i < cc; i += kCycThreads) {
+    int x, y, z;
+    cyc_xyz(i, A.n[c], x, y, z);
+    tc[i] = uc[i];
+    rhc[i] = rc[i] + cyc_L(uc, A.n[c], x, y, z, A.inv_h2[c]);
+  }
+  __syncthreads();
+}
+
+// level l's current u = P w (add = 0: the FMG step, w = level l - 1's u) or
+// u += P (w - t) (add = 1: the correction); trilinear, odd reflection at the
+// walls, the 8 terms in the order of k_fv_prolong
+__device__ void cyc_prolong(double* sm, const CycleArgs& A, int l, int add, unsigned cur) {
+  const int c = l - 1, cells = cyc_cells(A, l);
+  const double* w = cyc_arr(sm, A, c, (cur >> c) & 1);
+  const double* t = cyc_arr(sm, A, c, 3);
+  double* u = cyc_arr(sm, A, l, (cur >> l) & 1);
+  const int* nc = A.n[c];
+  for (int i = threadIdx.x; i < cells; i += kCycThreads) {
+    int fx, fy, fz;
+    cyc_xyz(i, A.n[l], fx, fy, fz);
+    const int p[3] = {fx >> 1, fy >> 1, fz >> 1};
+    const int k[3] = {fx & 1, fy & 1, fz & 1};
+    double s = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const double wt = (cx ? 0.25 : 0.75) * (cy ? 0.25 : 0.75) * (cz ? 0.25 : 0.75);
+          // the parent, or its neighbour toward the child
+          int a = p[0] + (cx ? (k[0] ? 1 : -1) : 0);
+          int b = p[1] + (cy ? (k[1] ? 1 : -1) : 0);
+          int d = p[2] + (cz ? (k[2] ? 1 : -1) : 0);
+          const double sg = mirror(nc[0], a) * mirror(nc[1], b) * mirror(nc[2], d);
+          const int ci = (d * nc[1] + b) * nc[0] + a;
+          const double cv = sg * (add ? w[ci] - t[ci] : w[ci]);
+          s += wt * cv;
+        }
+    u[i] = add ? u[i] + s : s;
+  }
+  __syncthreads();
+}
+
+// u_0 = A^-1 rhs_0 (into both LDS copies of level 0)
+__device__ void cyc_solve0(double* sm, const CycleArgs& A, const double* rhs, unsigned& cur) {
+  double* u0 = cyc_arr(sm, A, 0, 0);
+  double* u1 = cyc_arr(sm, A, 0, 1);
+  for (int i = threadIdx.x; i < A.m0; i += kCycThreads) {
+    double s = 0.0;
+    for (int j = 0; j < A.m0; ++j) s += A.Ainv[(long long)i * A.m0 + j] * rhs[j];
+    u0[i] = s;
+    u1[i] = s;
+  }
+  cur &= ~1u;
+  __syncthreads();
+}
+
+// FAS V-cycle from level top (right-hand side rt) down to the coarsest solve
+// and back up (Fig. 1)
+__device__ void cyc_vcycle(double* sm, const CycleArgs& A, int top, const double* rt,
+                           unsigned& cur) {
+  for (int l = top; l >= 1; --l) {
+    const double* rhs = l == top ? rt : cyc_arr(sm, A, l, 2);
+    cyc_cheb(sm, A, l, rhs, A.dpre, A.cpre[l], cur);
+    cyc_descend(sm, A, l, rhs, cur);
+  }
+  cyc_solve0(sm, A, top == 0 ? rt : cyc_arr(sm, A, 0, 2), cur);
+  for (int l = 1; l <= top; ++l) {
+    const double* rhs = l == top ? rt : cyc_arr(sm, A, l, 2);
+    cyc_prolong(sm, A, l, 1, cur);
+    cyc_cheb(sm, A, l, rhs, A.dpost, A.cpost[l], cur);
+  }
+}
+
+__global__ void __launch_bounds__(kCycThreads) k_fv_cycle(CycleArgs A) {
+  extern __shared__ double cyc_sm[];
+  double* sm = cyc_sm;
+  const int top = A.top, ct = cyc_cells(A, top);
+  unsigned cur = 0;  // bit l: the LDS copy of level l's u
+  if (A.mode == 0) {
+    double* f = cyc_arr(sm, A, top, 5);
+    for (int i = threadIdx.x; i < ct; i += kCycThreads) f[i] = A.src[i];
+    __syncthreads();
+    for (int l = top; l >= 1; --l) {  // f_{l-1} = R f_l (mean8's order)
+      const double* ff = cyc_arr(sm, A, l, 5);
+      double* fc = cyc_arr(sm, A, l - 1, 5);
+      const int* nf = A.n[l];
+      for (int i = threadIdx.x; i < cyc_cells(A, l - 1); i += kCycThreads) {
+        int I, J, K;
+        cyc_xyz(i, A.n[l - 1], I, J, K);
+        double sv = 0.0;
+        for (int cz = 0; cz < 2; ++cz)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a)
+              sv += ff[((2 * K + cz) * nf[1] + (2 * J + b)) * nf[0] + (2 * I + a)];
+        fc[i] = sv / 8.0;
+      }
+      __syncthreads();
+    }
+    cyc_solve0(sm, A, cyc_arr(sm, A, 0, 5), cur);
+    for (int l = 1; l <= top; ++l) {
+      const double* fl = cyc_arr(sm, A, l, 5);
+      cyc_prolong(sm, A, l, 0, cur);
+      cyc_cheb(sm, A, l, fl, A.dfmg, A.cfmg[l], cur);
+      cyc_vcycle(sm, A, l, fl, cur);
+    }
+  } else {
+    double* rt = cyc_arr(sm, A, top, 2);
+    double* u = cyc_arr(sm, A, top, 0);
+    for (int i = threadIdx.x; i < ct; i += kCycThreads) {
+      rt[i] = A.src[i];
+      u[i] = A.uin[i];
+    }
+    __syncthreads();
+    cyc_vcycle(sm, A, top, rt, cur);
+  }
+  const double* res = cyc_arr(sm, A, top, (cur >> top) & 1);
+  for (int i = threadIdx.x; i < ct; i += kCycThreads) {
+    A.uout0[i] = res[i];
+    A.uout1[i] = res[i];
+  }
+}
+
 // genuine cells of the finest segments into the caller's u (or a global
 // level's copy into u)
 __global__ void __launch_bounds__(kBlock) k_fv_gather(double* __restrict__ out,
@@ -732,6 +988,7 @@ struct fv27_plan {
   double* Ainv = nullptr;
   int m0 = 0;
   int64_t bytes = 0;
+  int Lc = -1;  // levels 0..Lc run in k_fv_cycle (-1: none)
   long long march_slots = 256 * 8;   // march workgroups resident at once (CUs x occupancy)
   long long march2_slots = 256 * 4;  // ... of the two-step march
   // schedule model of the last walk
@@ -1085,9 +1342,50 @@ struct Exec {
     launched();
   }
 
+  // levels 0..Lc in one workgroup: mode 0, the FMG stages 0..Lc (src = f of
+  // level Lc); mode 1, the V-cycle on level Lc (src = its right-hand side)
+  void cycle(int mode, const double* src) {
+    const int top = P->Lc;
+    Level& V = P->lv[top];
+    CycleArgs A{};
+    A.top = top;
+    A.mode = mode;
+    int off = 0;
+    for (int l = 0; l <= top; ++l) {
+      const Level& W = P->lv[l];
+      for (int d = 0; d < 3; ++d) A.n[l][d] = W.G.n[d];
+      A.inv_h2[l] = 1.0 / (W.h * W.h);
+      const double d = (121.0 / 24.0) / (W.h * W.h);
+      for (int j = 1; j <= P->p.cheb_pre; ++j) A.cpre[l][j - 1] = 1.0 / (d * cheb_root(j, P->p.cheb_pre));
+      for (int j = 1; j <= P->p.cheb_post; ++j)
+        A.cpost[l][j - 1] = 1.0 / (d * cheb_root(j, P->p.cheb_post));
+      for (int j = 1; j <= P->p.cheb_fmg; ++j) A.cfmg[l][j - 1] = 1.0 / (d * cheb_root(j, P->p.cheb_fmg));
+      A.o[l] = off;
+      off += kCycArrays * W.G.n[0] * W.G.n[1] * W.G.n[2];
+    }
+    A.dpre = P->p.cheb_pre;
+    A.dpost = P->p.cheb_post;
+    A.dfmg = P->p.cheb_fmg;
+    A.Ainv = P->Ainv;
+    A.m0 = P->m0;
+    A.src = src;
+    A.uin = V.u[V.cur];
+    A.uout0 = V.u[0];
+    A.uout1 = V.u[1];
+    const double ct = (double)V.G.n[0] * V.G.n[1] * V.G.n[2];
+    count(ct * (mode ? 32.0 : 24.0) + (double)P->m0 * P->m0 * 8.0);
+    if (dry) return;
+    hipLaunchKernelGGL(k_fv_cycle, dim3(1), dim3(kCycThreads), (size_t)off * sizeof(double), s, A);
+    launched();
+  }
+
   // FAS V-cycle on global level l (Fig. 1)
   void vcycle_global(int l, const double* rhs) {
     Level& V = P->lv[l];
+    if (l == P->Lc) {
+      cycle(1, rhs);
+      return;
+    }
     if (l == 0) {
       coarse_solve(rhs);
       return;
@@ -1125,7 +1423,8 @@ struct Exec {
 
   void f_hierarchy(const double* f) {
     P->lv[P->L - 1].f = const_cast<double*>(f);
-    for (int l = P->L - 1; l > 0; --l) {
+    // (k_fv_cycle restricts f below level Lc itself)
+    for (int l = P->L - 1; l > std::max(P->Lc, 0); --l) {
       Level& F = P->lv[l];
       Level& C = P->lv[l - 1];
       RestrictArgs A{};
@@ -1151,9 +1450,15 @@ struct Exec {
     fin = dry ? (double*)(uintptr_t)1 : u;  // (a dry walk only counts)
     fin_done = false;
     f_hierarchy(f);
-    // global FMG stages 0..T (Fig. 2)
-    coarse_solve(P->lv[0].f);
-    for (int l = 1; l <= P->T; ++l) {
+    // global FMG stages 0..T (Fig. 2); stages 0..Lc in one launch
+    int l0 = 1;
+    if (P->Lc >= 1) {
+      cycle(0, P->lv[P->Lc].f);
+      l0 = P->Lc + 1;
+    } else {
+      coarse_solve(P->lv[0].f);
+    }
+    for (int l = l0; l <= P->T; ++l) {
       prolong(l, 0);
       cheb(l, P->lv[l].f, true, P->p.cheb_fmg);
       vcycle_global(l, P->lv[l].f);
@@ -1226,6 +1531,15 @@ int32_t fv27_plan_create(const fv27_params* p, int32_t device, fv27_plan** out) 
   P->L = p->levels;
   P->K = p->sr_levels;
   P->T = P->L - 1 - P->K;
+  // the coarse-cycle kernel takes the global levels of at most kCycMaxCells
+  // cells (its LDS then stays under 64 KiB), if there are at least two
+  P->Lc = -1;
+  for (int l = 0; l <= P->T && l < fv::kCycMaxLevels; ++l) {
+    const int sh = P->L - 1 - l;
+    if ((long long)(p->n[0] >> sh) * (p->n[1] >> sh) * (p->n[2] >> sh) > fv::kCycMaxCells) break;
+    P->Lc = l;
+  }
+  if (P->Lc < 1) P->Lc = -1;
   try {
     fv::hipcheck(hipSetDevice(device), "hipSetDevice");
     P->lv.resize(P->L);
