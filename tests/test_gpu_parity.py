@@ -138,6 +138,19 @@ def test_sr_fmg_sweep_counts(N, L, K, S, J, sweeps):
     assert _rel(u, ref) <= TOL
 
 
+@pytest.mark.parametrize("N,L", [(56, 4), (80, 5)])
+def test_coarsest_edges_7_and_5(N, L):
+    """Coarsest edges 7 and 5: the coarse-level kernel's 14^3 level (up to two
+    cells of each colour per thread, edge read at run time) and its 10^3 and
+    5^3 levels; global and one SR level."""
+    _say("coarsest edge", N, L)
+    f = W.random_field(N, N + L)
+    u = fmg.solve(_gpu(f), L)
+    assert _rel(u, oracle.fmg(f, L)) <= TOL
+    us = fmg.solve(_gpu(f), L, sr_levels=1, segments=2, buffers=[2])
+    assert _rel(us, oracle.srfmg(f, L, 1, 2, [2])) <= TOL
+
+
 # --- segmental refinement --------------------------------------------------------
 
 SR_CASES = [
