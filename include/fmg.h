@@ -123,7 +123,12 @@ int32_t fmg_plan_execute(fmg_plan *plan, const double *f, double *u, void *strea
  *   target_blocks  workgroups a streaming pass aims for, 64..65536, or 0
  *                  (default): on levels above 64^3 the z chunks of each
  *                  pass over two copies are chosen for the fewest rounds of
- *                  resident workgroups times chunk depth, elsewhere 1024.
+ *                  resident workgroups times chunk depth, elsewhere 1024;
+ *   tile_x         width in columns of the xy tiles of the streaming passes
+ *                  over two copies: even, 8..256 (clamped per pass to what
+ *                  its halo and workgroup admit; the height follows from the
+ *                  workgroup's columns), or 0 (default): the shape that loads
+ *                  the fewest columns.
  * fmg_plan_set_tuning re-plans the schedule on the host (no device call);
  * FMG_EINVAL for out-of-range values.
  */
@@ -132,6 +137,7 @@ typedef struct {
   int32_t seg_inplace;
   int32_t box;
   int32_t target_blocks;
+  int32_t tile_x;
 } fmg_tuning;
 
 int32_t fmg_plan_get_tuning(const fmg_plan *plan, fmg_tuning *out);

@@ -231,6 +231,7 @@ struct fmg_plan {
   std::set<const void*> lds_attr;  // kernels already allowed the whole LDS
   std::vector<double*> ck;         // level checkpoints (empty: none)
   long long target_blocks = 0;  // workgroups a fused launch aims for (0: chosen per pass)
+  int tile_x = 0;               // tile width of the passes over two copies (0: cost model)
   int ncu = 256;                // compute units of the device
   int nxcd = 8;               // L2 domains (XCDs) the blocks are dealt to
   std::vector<int> J;  // J[l] for SR levels, indexed by level
@@ -530,23 +531,32 @@ struct Exec {
       // tile halo (one more for a residual epilogue, whose restriction also
       // needs even output extents: coarse cells are not split between tiles)
       constexpr int HH = NS + RES;
-      // tile shape: the fewest loaded columns covering the write region
+      // tile shape: the fewest loaded columns covering the write region, or
+      // the tuned width (clamped to what the pass admits)
       long long best = -1;
       // even widths: the kernel deals each row's columns to two colour classes
-      for (int tx = 2 * HH + 2; tx <= 256 && tx * (2 * HH + 2) <= NC; tx += 2) {
-        int ty = NC / tx;
-        if (ty > wext + 2 * HH) ty = wext + 2 * HH;
-        if (RES) ty &= ~1;
-        if (ty < 2 * HH + 2) continue;
-        long long cost = (long long)((wext + tx - 2 * HH - 1) / (tx - 2 * HH)) *
-                         ((wext + ty - 2 * HH - 1) / (ty - 2 * HH)) * tx * ty;
-        if (tx < 16) cost += cost / 4;  // short rows load poorly
-        if (best < 0 || cost < best) {
-          best = cost;
-          a.txw = tx;
-          a.tyw = ty;
+      auto search = [&](int tlo, int thi) {
+        for (int tx = tlo; tx <= thi && tx * (2 * HH + 2) <= NC; tx += 2) {
+          int ty = NC / tx;
+          if (ty > wext + 2 * HH) ty = wext + 2 * HH;
+          if (RES) ty &= ~1;
+          if (ty < 2 * HH + 2) continue;
+          long long cost = (long long)((wext + tx - 2 * HH - 1) / (tx - 2 * HH)) *
+                           ((wext + ty - 2 * HH - 1) / (ty - 2 * HH)) * tx * ty;
+          if (tx < 16) cost += cost / 4;  // short rows load poorly
+          if (best < 0 || cost < best) {
+            best = cost;
+            a.txw = tx;
+            a.tyw = ty;
+          }
         }
+      };
+      if (P->tile_x) {
+        const int tx = std::max(2 * HH + 2, std::min(P->tile_x, NC / (2 * HH + 2)) & ~1);
+        search(tx, tx);
       }
+      if (best < 0) search(2 * HH + 2, 256);
+      if (best < 0) throw hip_error("internal: no tile shape fits the pass");
       const int SX = a.txw - 2 * HH, SY = a.tyw - 2 * HH;
       a.ntx = (wext + SX - 1) / SX;
       a.nty = (wext + SY - 1) / SY;
@@ -1307,7 +1317,7 @@ static bool same_params(const fmg_params& a, const fmg_params& b) {
 static bool same_tuning(const fmg_tuning* a, const fmg_tuning* b) {
   if (!a || !b) return a == b;
   return a->max_stages == b->max_stages && a->seg_inplace == b->seg_inplace && a->box == b->box &&
-         a->target_blocks == b->target_blocks;
+         a->target_blocks == b->target_blocks && a->tile_x == b->tile_x;
 }
 
 // fork the caller's stream to the internal streams, enqueue every solve, join
@@ -1410,6 +1420,7 @@ int32_t fmg_plan_get_tuning(const fmg_plan* P, fmg_tuning* out) {
   out->seg_inplace = P->seg_inplace ? 1 : 0;
   out->box = P->use_box ? 1 : 0;
   out->target_blocks = (int32_t)P->target_blocks;
+  out->tile_x = P->tile_x;
   return FMG_OK;
 }
 
@@ -1420,10 +1431,13 @@ int32_t fmg_plan_set_tuning(fmg_plan* P, const fmg_tuning* t) {
     return fail(FMG_EINVAL, "seg_inplace and box must be 0 or 1");
   if (t->target_blocks != 0 && (t->target_blocks < 64 || t->target_blocks > 65536))
     return fail(FMG_EINVAL, "target_blocks must be 0 or in 64..65536");
+  if (t->tile_x != 0 && (t->tile_x < 8 || t->tile_x > 256 || (t->tile_x & 1)))
+    return fail(FMG_EINVAL, "tile_x must be 0 or even in 8..256");
   P->max_stages = t->max_stages;
   P->seg_inplace = t->seg_inplace != 0;
   P->use_box = t->box != 0;
   P->target_blocks = t->target_blocks;
+  P->tile_x = t->tile_x;
   try {
     settle_schedule(P);
   } catch (const hip_error& ex) {

@@ -49,7 +49,8 @@ class _KernelStat(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """fmg_tuning: performance knobs of a plan (see include/fmg.h)."""
     _fields_ = [("max_stages", ctypes.c_int32), ("seg_inplace", ctypes.c_int32),
-                ("box", ctypes.c_int32), ("target_blocks", ctypes.c_int32)]
+                ("box", ctypes.c_int32), ("target_blocks", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -230,7 +231,7 @@ class Plan:
         return t.as_dict()
 
     def set_tuning(self, **kw):
-        """Change performance knobs (max_stages, seg_inplace, box, target_blocks)."""
+        """Change performance knobs (max_stages, seg_inplace, box, target_blocks, tile_x)."""
         t = Tuning(**{**self.tuning, **kw})
         _check(lib().fmg_plan_set_tuning(self._h, ctypes.byref(t)))
 
@@ -341,7 +342,7 @@ class Batch:
             pass
 
 
-DEFAULT_TUNING = {"max_stages": 4, "seg_inplace": 1, "box": 1, "target_blocks": 0}
+DEFAULT_TUNING = {"max_stages": 4, "seg_inplace": 1, "box": 1, "target_blocks": 0, "tile_x": 0}
 
 
 def solve(f, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",

@@ -5,7 +5,11 @@ it times every candidate setting of the knobs on the device -- passes of 2 or
 4 half-sweeps, in-place segment smoothing, the box-resident smoother, the
 workgroup count a streaming pass aims for -- checks that each candidate's
 solution agrees with the default's (every setting computes the same solve up
-to rounding), and keeps the fastest.  Results persist in a JSON cache keyed
+to rounding), and keeps the fastest; then it tries the tile widths of
+TILE_WIDTHS for the streaming passes on that setting (the tile shape, which
+the library otherwise takes from its cost model).  Segment counts and
+buffer widths are not tuned: they change the segmental-refinement solution
+itself (its algebraic error), so they belong to the caller.  Results persist in a JSON cache keyed
 by the device, the library build and the configuration, so a batch of many
 right-hand sides tunes each distinct configuration once.
 
@@ -23,8 +27,9 @@ import torch
 
 from . import fmg
 
-CANDIDATES = [{"max_stages": ms, "seg_inplace": ip, "box": bx, "target_blocks": tb}
+CANDIDATES = [{"max_stages": ms, "seg_inplace": ip, "box": bx, "target_blocks": tb, "tile_x": 0}
               for ms, ip, bx, tb in itertools.product((2, 4), (1, 0), (1, 0), (0, 512, 1024, 2048))]
+TILE_WIDTHS = (16, 32, 64, 128)
 
 
 def default_cache_path():
@@ -79,9 +84,11 @@ def _time(plan, f, u, reps):
 
 
 def tune(N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), precision="fp64",
-         refine_iters=2, reps=5, cache=None, refresh=False, candidates=None):
+         refine_iters=2, reps=5, cache=None, refresh=False, candidates=None,
+         tile_widths=TILE_WIDTHS):
     """Best tuning (a dict of fmg_tuning fields) and its ms per solve, from the
-    cache or by timing every candidate on a seeded right-hand side."""
+    cache or by timing every candidate on a seeded right-hand side, then the
+    tile widths on the best candidate."""
     kw = dict(sr_levels=sr_levels, segments=segments, buffers=tuple(buffers), sweeps=tuple(sweeps),
               precision=precision, refine_iters=refine_iters)
     path = cache or default_cache_path()
@@ -99,8 +106,10 @@ def tune(N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), preci
     tol = 1e-12 if precision == "fp64" else 1e-5
     timings = {}
     best, best_ms = None, None
-    for c in candidates or CANDIDATES:
-        plan.set_tuning(**c)
+
+    def trial(c):
+        nonlocal best, best_ms
+        plan.set_tuning(**{**fmg.DEFAULT_TUNING, **c})
         ms = _time(plan, f, u, reps)
         err = float((u - ref).abs().max()) / max(scale, 1e-300)
         if err > tol:
@@ -108,6 +117,11 @@ def tune(N, levels, sr_levels=0, segments=1, buffers=(), sweeps=(2, 2, 1), preci
         timings[json.dumps(c, sort_keys=True)] = round(ms, 5)
         if best_ms is None or ms < best_ms:
             best, best_ms = dict(c), ms
+
+    for c in candidates or CANDIDATES:
+        trial(c)
+    for tx in tile_widths:
+        trial({**best, "tile_x": tx})
     plan.close()
     data = _load(path)
     data[key] = {"tuning": best, "ms": best_ms, "candidates": timings}
@@ -130,7 +144,8 @@ def _graph_ms(batch, fs, us, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_batch(problems, fs, us, streams=8, reps=3, cache=None, refresh=False, candidates=None):
+def tune_batch(problems, fs, us, streams=8, reps=3, cache=None, refresh=False, candidates=None,
+               tile_widths=TILE_WIDTHS):
     """Per-problem tunings for a batch (a list of dicts, one per problem),
     chosen by timing the batch graph on the given right-hand sides."""
     path = cache or default_cache_path()
@@ -160,15 +175,22 @@ def tune_batch(problems, fs, us, streams=8, reps=3, cache=None, refresh=False, c
             b.close()
 
     best_ms = run(best)
+
+    def attempt(ci, t):
+        nonlocal best, best_ms
+        if t == best[ci]:
+            return
+        trial = [dict(x) for x in best]
+        trial[ci] = t
+        ms = run(trial)
+        if ms < best_ms:
+            best, best_ms = trial, ms
+
     for ci in range(len(classes)):
         for c in cands:
-            trial = [dict(t) for t in best]
-            trial[ci] = dict(c)
-            if trial[ci] == best[ci]:
-                continue
-            ms = run(trial)
-            if ms < best_ms:
-                best, best_ms = trial, ms
+            attempt(ci, {**fmg.DEFAULT_TUNING, **c})
+        for tx in tile_widths:  # the tile widths on this class's best setting
+            attempt(ci, {**best[ci], "tile_x": tx})
     data = _load(path)
     data[key] = {"tunings": best, "ms": best_ms, "classes": [dict(c) for c in classes],
                  "streams": streams}

@@ -109,7 +109,9 @@ def test_transition_into_a_column_level(ms):
 
 @pytest.mark.parametrize("kw", [dict(max_stages=2), dict(seg_inplace=0), dict(box=0),
                                 dict(target_blocks=256), dict(max_stages=4, seg_inplace=0, box=0),
-                                dict(max_stages=2, seg_inplace=0, box=0)])
+                                dict(max_stages=2, seg_inplace=0, box=0), dict(tile_x=16),
+                                dict(tile_x=64, seg_inplace=0, box=0), dict(tile_x=8),
+                                dict(tile_x=256, max_stages=2)])
 def test_tuning_knobs_keep_the_solution(kw):
     print("tuning", kw, flush=True)
     N, L, K, S, J = 128, 7, 3, 4, [2, 4, 6]
@@ -124,6 +126,8 @@ def test_tuning_knobs_keep_the_solution(kw):
     assert _rel(g.execute(_gpu(f)), oracle.fmg(f, L)) <= TOL
     with pytest.raises(fmg.FMGError):
         plan.set_tuning(max_stages=3)
+    with pytest.raises(fmg.FMGError):
+        plan.set_tuning(tile_x=7)
     plan.close()
     g.close()
 
@@ -133,7 +137,9 @@ def test_autotuner_cache(tmp_path):
     cands = tune.CANDIDATES[:3]
     best, ms = tune.tune(64, 6, sr_levels=2, segments=4, buffers=(2, 2), reps=2, cache=path,
                          candidates=cands)
-    assert best in cands and ms > 0 and os.path.exists(path)
+    # a candidate, or a candidate with one of the tile widths
+    assert {**best, "tile_x": 0} in cands and best["tile_x"] in (0,) + tune.TILE_WIDTHS
+    assert ms > 0 and os.path.exists(path)
     again = tune.tune(64, 6, sr_levels=2, segments=4, buffers=(2, 2), cache=path, candidates=cands)
     assert again == (best, ms)
 
