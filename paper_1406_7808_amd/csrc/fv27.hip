@@ -1247,13 +1247,14 @@ struct Exec {
     const double d = (121.0 / 24.0) / (V.h * V.h);
     // steps in pairs, each pair one temporally blocked pass
     // (the two-step pass reads two cells beyond a wall: every extent >= 2).
-    // Segment levels, and global levels above 8M cells, keep one step per
+    // Segment levels, and global levels above 2M cells, keep one step per
     // pass: the two-step pass holds two workgroups of 512 threads per CU (106
     // VGPRs), too few to hide its per-plane latency, and measured slower there
-    // (512 x 256 x 256: 576 us against two 260 us steps; at 256 x 128 x 128
-    // it is faster, 67 against 72 us).
+    // (512 x 256 x 256: 576 us against two 260 us steps; 256 x 128 x 128: 68
+    // against two 31 us; every segment level of the model problem; at
+    // 128 x 64 x 64 the pair is faster, 17 against two 11 us).
     const long long cells = (long long)V.G.n[0] * V.G.n[1] * V.G.n[2];
-    const bool two = fused2 && !V.G.sr && cells <= (8ll << 20) && V.G.n[0] >= 2 &&
+    const bool two = fused2 && !V.G.sr && cells <= (2ll << 20) && V.G.n[0] >= 2 &&
                      V.G.n[1] >= 2 && V.G.n[2] >= 2;
     for (int j = 1; j <= degree;) {
       double* fo = last && (j == degree || (two && j + 1 == degree)) ? fin : nullptr;
@@ -1683,7 +1684,7 @@ int32_t fv27_op_cheb(double* u, const double* rhs, const int32_t* n, double h, i
   double* oth = tmp;
   hipError_t e = hipSuccess;
   // steps in pairs through the two-step pass (every extent >= 2), as the solver does on
-  // global levels of up to 8M cells
+  // global levels of up to 2M cells
   const bool two = n[0] >= 2 && n[1] >= 2 && n[2] >= 2;
   for (int j = 1; j <= degree && e == hipSuccess;) {
     A.u = cur;
