@@ -234,6 +234,17 @@ def test_full_size_sr_random_field():
     assert _rel(u, oracle.srfmg(f, 8, 3, 8, [2, 4, 6])) <= TOL
 
 
+def test_sr_seven_segments_per_dimension():
+    """224^3 with 7^3 = 343 segments per SR level (an odd segment count, more
+    workgroups than CUs on the box levels: 112^3 with 26^3 boxes and 56^3
+    with 22^3 boxes) on a random right-hand side, against the oracle."""
+    N, L, K, S, J = 224, 6, 3, 7, [2, 4, 6]
+    _say("sr seven segments", N, S)
+    f = W.random_field(N, 22407)
+    u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J)
+    assert _rel(u, oracle.srfmg(f, L, K, S, J)) <= TOL
+
+
 @pytest.fixture(scope="module")
 def polynomial512():
     return W.polynomial(512)
