@@ -940,18 +940,36 @@ struct Exec {
     int ce = mode == 0 ? cext(l) / 2 : Gc.n / P->S;
     double coarse = mode == 0 ? c_cells(G) / 8.0 : cube(Gc.n);
     double bytes = sizeof(T) * (16.0 * coarse + 2.0 * coarse);
+    // a global level onto the whole coarse global level (rhs on the fine
+    // level's own grid)
+    const bool glob = !G.ghost && !Gc.ghost && !gr.ghost && gr.n == G.n && mode == 0 && G.n >= 4;
     if (restricted) {
       // done in the smoothing pass's epilogue
     } else if (P->fused && cube(ce) * ns > 300000) {
       // the streaming pass on large targets; small ones are latency bound and
-      // take the one-thread-per-coarse-cell kernel
+      // take a one-thread-per-coarse-column march (global levels) or the
+      // one-thread-per-coarse-cell kernel
       descend_z(l, rhs, gr, mode, ce, bytes);
+    } else if (glob && P->fused) {
+      const int nc = Gc.n, zc = 1;  // short chunks: latency bound
+      run("k_resid_restrict_z", bytes,
+          dim3((nc + kResTX - 1) / kResTX, (nc + kResTY - 1) / kResTY, (nc + zc - 1) / zc),
+          dim3(kResTX * kResTY), k_resid_restrict_z<T>, (const T*)H.u[l], rhs, H.u[l - 1],
+          H.rhs[l - 1], G.n, zc);
     } else {
       run("k_resid_restrict", bytes, grid_for(cube(ce), ns), dim3(kBlock), k_resid_restrict<T>,
           (const T*)H.u[l], G, rhs, gr, H.u[l - 1], H.rhs[l - 1], Gc, mode, ce);
     }
     if (rhs_deferred) return;
     int nsc = mode == 0 ? ns : 1;
+    if (!Gc.ghost && whole_f && P->fused) {  // a global coarse level, F the whole level
+      const int nc = Gc.n, zc = 2;  // short chunks: latency bound
+      run("k_coarse_rhs_z", 4.0 * sizeof(T) * st_cells(Gc),
+          dim3((nc + kResTX - 1) / kResTX, (nc + kResTY - 1) / kResTY, (nc + zc - 1) / zc),
+          dim3(kResTX * kResTY), k_coarse_rhs_z<T>, (const T*)H.u[l - 1], H.rhs[l - 1],
+          H.t[l - 1], nc, zc);
+      return;
+    }
     run("k_coarse_rhs", 4.0 * sizeof(T) * st_cells(Gc), grid_for(cube(Gc.m), nsc), dim3(kBlock),
         k_coarse_rhs<T>, (const T*)H.u[l - 1], H.rhs[l - 1], H.t[l - 1], Gc, G, whole_f);
   }

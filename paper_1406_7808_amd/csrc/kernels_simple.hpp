@@ -331,6 +331,109 @@ __global__ void __launch_bounds__(kResTX * kResTY)
   }
 }
 
+// The FAS right-hand side of a global level whose F is the whole level
+// (k_coarse_rhs there) as a z march: t = u and r = r + L u, one thread per
+// column (x, y) over a chunk of zc planes, u's z neighbours carried in
+// registers, the in-plane ones read through the cache.  Same arithmetic, in
+// the same order, as k_coarse_rhs (nb_sum, apply_L).
+template <class T>
+__global__ void __launch_bounds__(kResTX * kResTY)
+    k_coarse_rhs_z(const T* __restrict__ u, T* __restrict__ r, T* __restrict__ t, int n, int zc) {
+  const int x = blockIdx.x * kResTX + (int)(threadIdx.x % kResTX);
+  const int y = blockIdx.y * kResTY + (int)(threadIdx.x / kResTX);
+  const int z0 = blockIdx.z * zc, z1 = min(n, z0 + zc);
+  if (x >= n || y >= n) return;  // (no barrier follows)
+  const long long nn = (long long)n * n, col = (long long)y * n + x;
+  const double n2 = (double)n * (double)n;
+  double um = z0 > 0 ? (double)u[(z0 - 1) * nn + col] : 0.0;
+  T uv = u[z0 * nn + col];
+  for (int z = z0; z < z1; ++z) {
+    const long long id = z * nn + col;
+    const T upv = z + 1 < n ? u[id + nn] : (T)0;
+    const double uc = (double)uv, up = (double)upv;
+    double s = 0.0;
+    int nb = 0;
+    if (x > 0) s += (double)u[id - 1]; else ++nb;
+    if (x < n - 1) s += (double)u[id + 1]; else ++nb;
+    if (y > 0) s += (double)u[id - n]; else ++nb;
+    if (y < n - 1) s += (double)u[id + n]; else ++nb;
+    if (z > 0) s += um; else ++nb;
+    if (z < n - 1) s += up; else ++nb;
+    t[id] = uv;
+    r[id] = (T)((double)r[id] + (s - (double)(6 + nb) * uc) * n2);
+    um = uc;
+    uv = upv;
+  }
+}
+
+// Residual and restriction of a global level onto the whole coarse global
+// level (k_resid_restrict there, mode 0) as a z march: one thread per coarse
+// column (X, Y) over a chunk of zc coarse planes.  The 2 x 2 fine columns
+// under it carry u of fine planes 2Z - 1 .. 2Z + 2 in registers from one
+// coarse plane to the next; in-plane neighbours outside the 2 x 2 block come
+// through the cache.  Same arithmetic, in the same order, as
+// k_resid_restrict (children z, y, x; nb_sum; apply_L).
+template <class T>
+__global__ void __launch_bounds__(kResTX * kResTY)
+    k_resid_restrict_z(const T* __restrict__ u, const T* __restrict__ rhs, T* __restrict__ uc,
+                       T* __restrict__ rc, int n, int zc) {
+  const int nc = n / 2;
+  const int X = blockIdx.x * kResTX + (int)(threadIdx.x % kResTX);
+  const int Y = blockIdx.y * kResTY + (int)(threadIdx.x / kResTX);
+  const int Z0 = blockIdx.z * zc, Z1 = min(nc, Z0 + zc);
+  if (X >= nc || Y >= nc) return;  // (no barrier follows)
+  const long long nn = (long long)n * n;
+  const int x0 = 2 * X, y0 = 2 * Y;
+  const long long c0 = (long long)y0 * n + x0;  // fine column (x0, y0)
+  const double n2 = (double)n * (double)n;
+  // w[p][b][a]: u at fine (x0 + a, y0 + b, 2Z - 1 + p), 0 outside the domain
+  double w[4][2][2];
+  auto load = [&](int k, double (&d)[2][2]) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        d[b][a] = (k >= 0 && k < n) ? (double)u[k * nn + c0 + b * n + a] : 0.0;
+  };
+  load(2 * Z0 - 1, w[0]);
+  load(2 * Z0, w[1]);
+  for (int Z = Z0; Z < Z1; ++Z) {
+    load(2 * Z + 1, w[2]);
+    load(2 * Z + 2, w[3]);
+    double su = 0.0, sr = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int i = x0 + a, j = y0 + b, k = 2 * Z + c;
+          const long long id = k * nn + c0 + b * n + a;
+          const double v = w[c + 1][b][a];
+          su += v;
+          double s = 0.0;
+          int nb = 0;
+          if (a == 1) s += w[c + 1][b][0]; else if (i > 0) s += (double)u[id - 1]; else ++nb;
+          if (a == 0) s += w[c + 1][b][1]; else if (i < n - 1) s += (double)u[id + 1]; else ++nb;
+          if (b == 1) s += w[c + 1][0][a]; else if (j > 0) s += (double)u[id - n]; else ++nb;
+          if (b == 0) s += w[c + 1][1][a]; else if (j < n - 1) s += (double)u[id + n]; else ++nb;
+          if (k > 0) s += w[c][b][a]; else ++nb;
+          if (k < n - 1) s += w[c + 2][b][a]; else ++nb;
+          sr += (double)rhs[id] - (s - (double)(6 + nb) * v) * n2;
+        }
+    const long long ic = ((long long)Z * nc + Y) * nc + X;
+    uc[ic] = (T)(su / 8.0);
+    rc[ic] = (T)(sr / 8.0);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        w[0][b][a] = w[2][b][a];
+        w[1][b][a] = w[3][b][a];
+      }
+  }
+}
+
 // u (+)= e
 template <class T>
 __global__ void k_update64(double* __restrict__ u, const T* __restrict__ e, long long cnt,
