@@ -622,9 +622,11 @@ struct Exec {
   // per thread with its whole z chunk in registers (two copies); RES: the
   // pass also restricts u and the residual to level l - 1; fas: it first
   // forms the FAS right-hand side rhs + L u and t = u of this level
-  template <int NS, int PRO, int RES>
+  // ZC: output planes per z chunk (each chunk also loads 2 (NS + RES) halo
+  // planes)
+  template <int NS, int PRO, int RES, int ZC = 2>
   void smooth_cols(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, int fas = 0) {
-    constexpr int NT = 1024, ZC = 2, HH = NS + RES;
+    constexpr int NT = 1024, HH = NS + RES;
     const Geo& G = H.geo[l];
     const int n = G.n;
     if (G.ghost || nseg(l) != 1 || (RES && l < 1))
@@ -868,7 +870,11 @@ struct Exec {
       } else if (pr == PRO_LOAD && rmode == 0 && !inpl && cols_level(l) && st == ns) {
         // ... and over two copies on the small global levels
         const int pf = first ? fas : 0;
+        // four-stage passes with the epilogue load 2 (4 + 1) halo planes per
+        // chunk: on 64^3 and up, 4-plane chunks (35 against 50 us at 64^3; at
+        // 32^3, and for the other passes, 2-plane chunks are faster)
         if (ns == 2) smooth_cols<2, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, pf);
+        else if (G.n >= 64) smooth_cols<4, PRO_LOAD, 1, 4>(l, rhs, gr, d, dt, Gc, pf);
         else smooth_cols<4, PRO_LOAD, 1>(l, rhs, gr, d, dt, Gc, pf);
         restricted = true;
       } else if (pr == PRO_CORRECT) {
