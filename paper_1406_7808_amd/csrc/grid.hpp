@@ -32,23 +32,36 @@ struct Box {
   long long base;
 };
 
+// floor(a / b) for 0 <= a < 2^22 and 1 <= b < 2^11.  The product with the
+// hardware reciprocal (relative error below 2^-22) lies within one of a / b,
+// so its truncation is the quotient or one off, which one test corrects.
+// (A 32-bit integer division takes some 40 vector instructions.)
+__device__ inline int udiv_small(int a, int b) {
+  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  const int r = a - q * b;
+  q += r >= b ? 1 : 0;
+  q -= r < 0 ? 1 : 0;
+  return q;
+}
+
 // A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
 // from linear index c0 in strides of `stride`: one set of divisions at the
 // start, then additions with at most one carry per dimension.  A thread whose
-// c0 is at or past lim has no cell and skips the divisions.
+// c0 is at or past lim has no cell and skips the divisions.  For boxes that
+// fit a workgroup's LDS: c0 and stride below 2^22, ex * ey below 2^11.
 struct Walk3 {
   int i, j, k, di, dj, dk, ex, ey;
   __device__ Walk3(int c0, int stride, int ex_, int ey_, int lim = 0x7fffffff)
       : i(0), j(0), k(0), di(0), dj(0), dk(0), ex(max(ex_, 1)), ey(max(ey_, 1)) {
     if (c0 >= lim) return;
     const int exy = ex * ey;  // an empty box walks a 1 x 1 plane and is never read
-    k = c0 / exy;
+    k = udiv_small(c0, exy);
     const int r = c0 - k * exy;
-    j = r / ex;
+    j = udiv_small(r, ex);
     i = r - j * ex;
-    dk = stride / exy;
+    dk = udiv_small(stride, exy);
     const int rs = stride - dk * exy;
-    dj = rs / ex;
+    dj = udiv_small(rs, ex);
     di = rs - dj * ex;
   }
   __device__ void next() {
@@ -87,6 +100,23 @@ __host__ __device__ inline Box seg_box(const Geo& G, int q) {
   Box B;
   int s = (G.S > 1) ? q : 0;
   int p[3] = {s % G.S, (s / G.S) % G.S, s / (G.S * G.S)};
+  for (int d = 0; d < 3; ++d) {
+    int a = p[d] * G.g - G.J, b = (p[d] + 1) * G.g + G.J;
+    B.a[d] = a < 0 ? 0 : a;
+    B.b[d] = b > G.n ? G.n : b;
+    B.o[d] = B.a[d] - G.ghost;
+  }
+  B.base = (long long)s * G.sstride;
+  return B;
+}
+
+// seg_box in device code with the small-operand division (at most 40
+// segments per dimension: S^3 below 2^22, S^2 below 2^11)
+__device__ inline Box seg_box_d(const Geo& G, int q) {
+  Box B;
+  const int s = (G.S > 1) ? q : 0;
+  const int sy = udiv_small(s, G.S), sz = udiv_small(sy, G.S);
+  const int p[3] = {s - sy * G.S, sy - sz * G.S, sz};
   for (int d = 0; d < 3; ++d) {
     int a = p[d] * G.g - G.J, b = (p[d] + 1) * G.g + G.J;
     B.a[d] = a < 0 ? 0 : a;

@@ -119,17 +119,6 @@ __device__ inline int pidx(int n, int x, int y, int z) {
   return ((z + 1) * p + (y + 1)) * p + (x + 1);
 }
 
-// floor(a / b) for 0 <= a < 2^22 and 1 <= b < 2^11.  The product with the
-// hardware reciprocal (relative error below 2^-22) lies within one of a / b,
-// so its truncation is the quotient or one off, which one test corrects.
-__device__ inline int udiv_small(int a, int b) {
-  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
-  const int r = a - q * b;
-  q += r >= b ? 1 : 0;
-  q -= r < 0 ? 1 : 0;
-  return q;
-}
-
 // cell (i, j, k) of an ex x ey x * box walked from linear index c0 in strides
 // of `stride` (the grid-wide Walk3 with the small-operand division)
 struct CWalk {

@@ -653,7 +653,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   const Geo gu = a.gu;
   const int q = blockIdx.x, n = gu.n, m = gu.m, m2 = m * m, mc = m * m2;
   const int NT = blockDim.x;
-  const Box B = seg_box(gu, q), Br = seg_box(a.gr, q), Bc = seg_box(a.gc, q);
+  const Box B = seg_box_d(gu, q), Br = seg_box_d(a.gr, q), Bc = seg_box_d(a.gc, q);
   T* __restrict__ ub = a.u + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
   const bool fas = PRO == PRO_LOAD && a.fas > 0;
@@ -680,7 +680,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
     const int cpr = (int)((run + 1023) >> 10);  // chunks per run
     const int nch = (zh - zl) * cpr;
     for (int ch = wv; ch < nch; ch += nw) {
-      const int pz = zl + ch / cpr, c = ch - (ch / cpr) * cpr;
+      const int cq = udiv_small(ch, cpr), pz = zl + cq, c = ch - cq * cpr;
       const long long o = ((long long)pz * m + yl) * m * (long long)sizeof(T) + (long long)c * 1024;
       if ((long long)c * 1024 + ln * 16 < run)
         __builtin_amdgcn_global_load_lds(src + o + ln * 16,
@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   int ns = 0;
   int flo[3] = {0, 0, 0}, fhi[3] = {n, n, n};
   if (fas && a.fas == 1) {
-    const Box Bf = seg_box(a.gf, q);
+    const Box Bf = seg_box_d(a.gf, q);
     for (int d = 0; d < 3; ++d) {
       flo[d] = Bf.a[d] / 2;
       fhi[d] = Bf.b[d] / 2;
@@ -749,7 +749,8 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
         const int w = side ? wh : wl, s0 = side ? m - wh : 0;
         const int cnt = w * m2;
         for (int c = threadIdx.x; c < cnt; c += NT) {
-          const int k = s0 + c / m2, r = c - (c / m2) * m2, i = r % m, j = r / m;
+          const int cz = udiv_small(c, m2), r = c - cz * m2, j = udiv_small(r, m), i = r - j * m;
+          const int k = s0 + cz;
           // k runs along dimension d, (i, j) over the other two
           const int l = d == 0 ? (j * m + i) * m + k : d == 1 ? (j * m + k) * m + i : (k * m + j) * m + i;
           bu[l] = (T)0;
@@ -790,7 +791,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
   // FAS prologue: t = the loaded box, where the finer level's correction reads
   // it (the parents of the finer segment's stored cells, inside the domain)
   if (fas) {
-    const Box Bf = seg_box(a.gf, q);
+    const Box Bf = seg_box_d(a.gf, q);
     int tlo[3], tw[3];
     for (int d = 0; d < 3; ++d) {
       int lo = Bf.o[d] >> 1, hi = (Bf.o[d] + a.gf.m - 1) >> 1;
@@ -908,14 +909,15 @@ __global__ void __launch_bounds__(kBoxThreads) k_smooth_box(BoxArgs<T> a) {
       hi[d] = B.b[d] / 2;
     }
   } else {
-    const int S = gu.S, e = a.gcr.n / S;
-    const int p[3] = {q % S, (q / S) % S, q / (S * S)};
+    const int S = gu.S, e = udiv_small(a.gcr.n, S);
+    const int qy = udiv_small(q, S), qz = udiv_small(qy, S);
+    const int p[3] = {q - qy * S, qy - qz * S, qz};
     for (int d = 0; d < 3; ++d) {
       lo[d] = p[d] * e;
       hi[d] = (p[d] + 1) * e;
     }
   }
-  const Box Bo = seg_box(a.gcr, q);
+  const Box Bo = seg_box_d(a.gcr, q);
   const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ncc = ex * ey * (hi[2] - lo[2]);
   auto child0 = [&](const Walk3& w, long long& id) -> int {  // LDS index of the (0,0,0) child
     const int I = w.i, J = w.j, K = w.k;
