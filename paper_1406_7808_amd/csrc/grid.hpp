@@ -44,6 +44,19 @@ __device__ inline int udiv_small(int a, int b) {
   return q;
 }
 
+// udiv_small of wavefront-uniform operands, its result kept in a scalar
+// register
+__device__ inline int udiv_uniform(int a, int b) {
+  return __builtin_amdgcn_readfirstlane(udiv_small(a, b));
+}
+
+// floor(a / b) for a >= 0, b >= 1: the small-operand division where its
+// range holds (a branch that is uniform when the operands are), else the
+// integer division
+__device__ inline int udiv_fast(int a, int b) {
+  return ((unsigned)a < (1u << 22) && (unsigned)(b - 1) < (1u << 11) - 1) ? udiv_small(a, b) : a / b;
+}
+
 // A thread's walk over the cells of an ex x ey x (ez) box in x-fastest order,
 // from linear index c0 in strides of `stride`: one set of divisions at the
 // start, then additions with at most one carry per dimension.  A thread whose
@@ -115,7 +128,7 @@ __host__ __device__ inline Box seg_box(const Geo& G, int q) {
 __device__ inline Box seg_box_d(const Geo& G, int q) {
   Box B;
   const int s = (G.S > 1) ? q : 0;
-  const int sy = udiv_small(s, G.S), sz = udiv_small(sy, G.S);
+  const int sy = udiv_uniform(s, G.S), sz = udiv_uniform(sy, G.S);
   const int p[3] = {s - sy * G.S, sy - sz * G.S, sz};
   for (int d = 0; d < 3; ++d) {
     int a = p[d] * G.g - G.J, b = (p[d] + 1) * G.g + G.J;

@@ -63,12 +63,14 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
   int tid = blockIdx.x;
   {
     const int nt = a.ntx * a.nty * a.ntz;
-    const int per = (nt + a.nxcd - 1) / a.nxcd;
-    const int t2 = (tid % a.nxcd) * per + tid / a.nxcd;
+    const int per = udiv_fast(nt + a.nxcd - 1, a.nxcd);
+    const int tq = udiv_fast(tid, a.nxcd);
+    const int t2 = (tid - tq * a.nxcd) * per + tq;
     if (t2 >= nt) return;
     tid = t2;
   }
-  const int ti = tid % a.ntx, tj = (tid / a.ntx) % a.nty, tk = tid / (a.ntx * a.nty);
+  const int tq1 = udiv_fast(tid, a.ntx), tk = udiv_fast(tq1, a.nty);
+  const int ti = tid - tq1 * a.ntx, tj = tq1 - tk * a.nty;
   const int ox = ti * sx, oy = tj * sy, oz = tk * ZC, z0 = oz - HZ;
   // slots [0, NT/2) hold the columns of even (cx + cy), [NT/2, NT) the odd
   // ones (txw is even, so every row has txw/2 of each); a column's rank in
@@ -81,7 +83,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
   // the same class, as a wavefront-uniform value (NT/2 is a multiple of 64)
   const int hw = __builtin_amdgcn_readfirstlane(t) >= NT / 2 ? 1 : 0;
   const bool col = rk < tw2 * tyw;
-  const int cy = col ? rk / tw2 : 0;
+  const int cy = col ? udiv_small(rk, tw2) : 0;  // tw2 <= 128
   const int cx = col ? 2 * (rk - cy * tw2) + ((cy + hc) & 1) : 0;
   const int x = ox - H + cx, y = oy - H + cy;
   const bool st = col && x >= 0 && x < n && y >= 0 && y < n;
@@ -94,7 +96,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
   const int ir = act ? rk : tw2;
   const int xn = oc + ir - 1 + (cx & 1), yn = oc + ir - tw2, yp = oc + ir + tw2;
   const int nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
-  const Box B = seg_box(a.gu, 0), Br = seg_box(a.gr, 0);
+  const Box B = seg_box_d(a.gu, 0), Br = seg_box_d(a.gr, 0);
   const long long pu = st ? at(a.gu, B, x, y, 0) : 0, pr = st ? at(a.gr, Br, x, y, 0) : 0;
   const long long mu = (long long)a.gu.m * a.gu.m, mr = (long long)a.gr.m * a.gr.m;
   if (t < 7) invd[t] = (T)1 / (T)(6 + t);  // read after a barrier
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
   if constexpr (PRO == PRO_CORRECT) {
     // u + (w - t) of the parent (Eq. 4's correction, piecewise constant):
     // fine planes 2K, 2K + 1 of the chunk share parent plane z0 / 2 + K
-    const Box Bc = seg_box(a.gc, 0);
+    const Box Bc = seg_box_d(a.gc, 0);
     const int nc = a.gc.n;
     const long long pc = st ? at(a.gc, Bc, x >> 1, y >> 1, 0) : 0;
     const long long mc = (long long)a.gc.m * a.gc.m;
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
     // columns (X0, Y0), (X1, Y0), (X0, Y1), (X1, Y1) with X1 the next (odd x)
     // or previous coarse column; a column past the wall is X0 with sign -1.
     // Coarse planes z0 / 2 - 1 + K, K = 0 .. Z / 2 + 1, reflected likewise.
-    const Box Bc = seg_box(a.gc, 0);
+    const Box Bc = seg_box_d(a.gc, 0);
     const int nc = a.gc.n;
     const int X0 = x >> 1, Y0 = y >> 1;
     int X1 = (x & 1) ? X0 + 1 : X0 - 1, Y1 = (y & 1) ? Y0 + 1 : Y0 - 1;
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
     const bool own = outc && (x & 1) == 0 && (y & 1) == 0;
     const int od = cx & 1, pn = oc + rk;
     if (own) {
-      const Box Bo = seg_box(a.gcr, 0);
+      const Box Bo = seg_box_d(a.gcr, 0);
 #pragma unroll
       for (int k = 0; k < ZC / 2; ++k) {
         const int Zc = (oz >> 1) + k;

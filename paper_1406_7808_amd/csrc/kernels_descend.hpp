@@ -41,15 +41,16 @@ struct DescArgs {
 // target coarse box of segment q
 __host__ __device__ inline void desc_target(const Geo& gu, const Geo& gc, int q, int mode,
                                             int lo[3], int hi[3]) {
-  const Box B = seg_box(gu, q);
+  const Box B = seg_box_d(gu, q);
   if (mode == 0) {
     for (int d = 0; d < 3; ++d) {
       lo[d] = B.a[d] / 2;
       hi[d] = B.b[d] / 2;
     }
   } else {
-    const int S = gu.S, e = gc.n / S;
-    const int p[3] = {q % S, (q / S) % S, q / (S * S)};
+    const int S = gu.S, e = udiv_small(gc.n, S);  // at most 40 segments per dimension
+    const int qy = udiv_small(q, S), qz = udiv_small(qy, S);
+    const int p[3] = {q - qy * S, qy - qz * S, qz};
     for (int d = 0; d < 3; ++d) {
       lo[d] = p[d] * e;
       hi[d] = (p[d] + 1) * e;
@@ -67,19 +68,21 @@ k_descend_z(DescArgs<T> a) {
   const Geo gu = a.gu;
   const int q = blockIdx.y;
   const int n = gu.n;
-  const Box B = seg_box(gu, q), Br = seg_box(a.gr, q), Bc = seg_box(a.gc, q);
+  const Box B = seg_box_d(gu, q), Br = seg_box_d(a.gr, q), Bc = seg_box_d(a.gc, q);
   int lo[3], hi[3];
   desc_target(gu, a.gc, q, a.mode, lo, hi);
 
   int tid = blockIdx.x;
   {
     const int nt = a.ntx * a.nty * a.ntz;
-    const int per = (nt + a.nxcd - 1) / a.nxcd;
-    const int t2 = (tid % a.nxcd) * per + tid / a.nxcd;
+    const int per = udiv_fast(nt + a.nxcd - 1, a.nxcd);
+    const int tq = udiv_fast(tid, a.nxcd);
+    const int t2 = (tid - tq * a.nxcd) * per + tq;
     if (t2 >= nt) return;
     tid = t2;
   }
-  const int ti = tid % a.ntx, tj = (tid / a.ntx) % a.nty, tk = tid / (a.ntx * a.nty);
+  const int tq1 = udiv_fast(tid, a.ntx), tk = udiv_fast(tq1, a.nty);
+  const int ti = tid - tq1 * a.ntx, tj = tq1 - tk * a.nty;
   const int I0 = lo[0] + ti * a.ctx, J0 = lo[1] + tj * a.cty, K0 = lo[2] + tk * a.kc;
   if (I0 >= hi[0] || J0 >= hi[1] || K0 >= hi[2]) return;
   const int I1 = I0 + a.ctx < hi[0] ? I0 + a.ctx : hi[0];
@@ -98,7 +101,7 @@ k_descend_z(DescArgs<T> a) {
   for (int r = 0; r < RY; ++r) {
     const int c = threadIdx.x + NT * r;
     const bool col = c < fw * fh;
-    const int cy = c / fw, cx = c - cy * fw;
+    const int cy = udiv_fast(c, fw), cx = c - cy * fw;
     const int x = 2 * I0 - 1 + cx, y = 2 * J0 - 1 + cy;
     // the footprint is x in [2 I0 - 1, 2 I1], y likewise (inside the storage
     // box: C plus its ghost layer); columns past a clipped tile stay idle
@@ -193,7 +196,7 @@ k_descend_z(DescArgs<T> a) {
           for (int r = 0; r < RY; ++r) {
             if (fl[r] & 4u) {
               const int c = ci[r];
-              const int cy = c / fw, cx = c - cy * fw;
+              const int cy = udiv_fast(c, fw), cx = c - cy * fw;
               const int I = I0 + ((cx - 1) >> 1), J = J0 + ((cy - 1) >> 1);
               const double tu = (lsu[c] + lsu[c + 1]) + (lsu[c + fw] + lsu[c + fw + 1]);
               const double tr = (lsr[c] + lsr[c + 1]) + (lsr[c + fw] + lsr[c + fw + 1]);

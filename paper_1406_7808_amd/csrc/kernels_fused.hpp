@@ -105,7 +105,7 @@ k_smooth_z(SmoothArgs<T> a) {
 
   const Geo gu = a.gu;
   const int q = blockIdx.y;
-  const Box B = seg_box(gu, q);
+  const Box B = seg_box_d(gu, q);
   const int n = gu.n;
   const bool inpl = a.inplace != 0;
   // tile halo: NS columns; a residual over two copies needs the neighbours of
@@ -117,12 +117,14 @@ k_smooth_z(SmoothArgs<T> a) {
   int tid = blockIdx.x;
   {
     int nt = a.ntx * a.nty * a.ntz;
-    int per = (nt + a.nxcd - 1) / a.nxcd;
-    int t2 = (tid % a.nxcd) * per + tid / a.nxcd;
+    int per = udiv_fast(nt + a.nxcd - 1, a.nxcd);
+    const int tq = udiv_fast(tid, a.nxcd);
+    int t2 = (tid - tq * a.nxcd) * per + tq;
     if (t2 >= nt) return;
     tid = t2;
   }
-  const int ti = tid % a.ntx, tj = (tid / a.ntx) % a.nty, tk = tid / (a.ntx * a.nty);
+  const int tq1 = udiv_fast(tid, a.ntx), tk = udiv_fast(tq1, a.nty);
+  const int ti = tid - tq1 * a.ntx, tj = tq1 - tk * a.nty;
 
   // load region: every stored cell inside the domain.  The tiles partition
   // the load region (two copies) or C (in place); in place, a correction
@@ -136,7 +138,8 @@ k_smooth_z(SmoothArgs<T> a) {
   }
   // genuine region of the segment (output epilogue)
   const int S = gu.S;
-  const int gx0 = (q % S) * gu.g, gy0 = ((q / S) % S) * gu.g, gz0 = (q / (S * S)) * gu.g;
+  const int qy = udiv_uniform(q, S), qz = udiv_uniform(qy, S);  // at most 40 segments per dimension
+  const int gx0 = (q - qy * S) * gu.g, gy0 = (qy - qz * S) * gu.g, gz0 = qz * gu.g;
   const int tx0 = inpl ? B.a[0] : wlo[0], ty0 = inpl ? B.a[1] : wlo[1];
   const int tz0 = inpl ? B.a[2] : wlo[2], tz1 = inpl ? B.b[2] : whi[2];
   const int ox = tx0 + ti * sx, oy = ty0 + tj * sy, oz = tz0 + tk * a.zc;
@@ -156,8 +159,8 @@ k_smooth_z(SmoothArgs<T> a) {
   const int p0 = oz - NS - ((RES && !inpl) ? 1 : 0), p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
-  const Box Br = seg_box(a.gr, q);
-  const Box Bc = seg_box(a.gc, q);
+  const Box Br = seg_box_d(a.gr, q);
+  const Box Bc = seg_box_d(a.gc, q);
   T* __restrict__ wb = a.u + B.base;
   const T* __restrict__ ub = a.uin + B.base;
   const T* __restrict__ rb = a.rhs + Br.base;
@@ -211,7 +214,8 @@ k_smooth_z(SmoothArgs<T> a) {
   int tco = 0;  // this thread's coarse column (offset in the coarse box), if any
   bool tcv = false;
   if (PRO != PRO_LOAD && (int)threadIdx.x < ctn) {
-    const int X = cX0 + (int)threadIdx.x % ctx, Y = cY0 + (int)threadIdx.x / ctx;
+    const int tyq = udiv_small((int)threadIdx.x, ctx);  // ctx <= 131
+    const int X = cX0 + (int)threadIdx.x - tyq * ctx, Y = cY0 + tyq;
     tcv = X >= 0 && X < a.gc.n && Y >= 0 && Y < a.gc.n && X >= Bc.o[0] && X < Bc.o[0] + a.gc.m &&
           Y >= Bc.o[1] && Y < Bc.o[1] + a.gc.m;
     tco = tcv ? (Y - Bc.o[1]) * a.gc.m + (X - Bc.o[0]) : 0;
@@ -225,7 +229,7 @@ k_smooth_z(SmoothArgs<T> a) {
     const int sl = threadIdx.x + NT * r;
     const int h = sl >= NC / 2 ? 1 : 0, i = sl - h * (NC / 2), tw2 = txw >> 1, k = h ^ c0;
     const bool col = i < tw2 * tyw;
-    const int cy = col ? i / tw2 : 0;
+    const int cy = col ? udiv_small(i, tw2) : 0;  // tw2 <= 128
     // (x + y) parity of the tile column (cx, cy) is (ox + oy + cx + cy) & 1
     const int cx = col ? 2 * (i - cy * tw2) + ((cy + k + ox + oy) & 1) : 0;
     const int x = ox - H + cx, y = oy - H + cy;
@@ -461,7 +465,7 @@ k_smooth_z(SmoothArgs<T> a) {
       // coarse plane (zr - 1) / 2 (uniform over the block)
       const int zc = (zr - 1) >> 1, cb = zc & 1;
       const bool zt = a.rmode == 0 || (zr - 1 >= gz0 && zr - 1 < gz0 + gu.g);
-      const Box Bo = seg_box(a.gcr, q);
+      const Box Bo = seg_box_d(a.gcr, q);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (zt && (ok[r] & 256u)) {
@@ -531,18 +535,16 @@ template <class T>
 __global__ void __launch_bounds__(256) k_interp_z(T* __restrict__ u, Geo gu,
                                                   const T* __restrict__ c, Geo gc, int zc, int ce) {
   const int q = blockIdx.y;
-  const Box B = seg_box(gu, q), Bc = seg_box(gc, q);
+  const Box B = seg_box_d(gu, q), Bc = seg_box_d(gc, q);
   const int n = gu.n, nc = gc.n;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
     lo[d] = B.o[d] < 0 ? 0 : B.o[d];
     hi[d] = B.o[d] + gu.m > n ? n : B.o[d] + gu.m;
   }
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int cx = (int)(t % ce);
-  t /= ce;
-  const int cy = (int)(t % ce);
-  const int kz = (int)(t / ce);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // the grid stays below 2^31 threads
+  const int t1 = udiv_fast(t, ce), kz = udiv_fast(t1, ce);
+  const int cx = t - t1 * ce, cy = t1 - kz * ce;
   const int x = lo[0] + cx, y = lo[1] + cy, z0 = lo[2] + kz * zc;
   if (x >= hi[0] || y >= hi[1] || z0 >= hi[2]) return;
   const int z1 = z0 + zc < hi[2] ? z0 + zc : hi[2];
