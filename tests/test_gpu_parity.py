@@ -245,6 +245,17 @@ def test_sr_seven_segments_per_dimension():
     assert _rel(u, oracle.srfmg(f, L, K, S, J)) <= TOL
 
 
+def test_sr_forty_segments_per_dimension():
+    """The largest segment count per dimension (40, 64000 segments of 2^3
+    genuine cells at 80^3): segment coordinates and box walks at the top of
+    the range of the kernels' small-operand divisions."""
+    N, L, K, S, J = 80, 5, 1, 40, [2]
+    _say("sr forty segments", N, S)
+    f = W.random_field(N, 4040)
+    u = fmg.solve(_gpu(f), L, sr_levels=K, segments=S, buffers=J)
+    assert _rel(u, oracle.srfmg(f, L, K, S, J)) <= TOL
+
+
 @pytest.fixture(scope="module")
 def polynomial512():
     return W.polynomial(512)
