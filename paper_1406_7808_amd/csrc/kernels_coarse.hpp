@@ -598,11 +598,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse(CoarseArgs<T> g) {
       if (s < 0) blk_interp(ul, n, sm + g.ou[l - 1]);
       if (s > lt) {
         if (n == 16) blk_correct<T, 16>(ul, n, sm + g.ou[l - 1], sm + g.ot[l - 1]);
+        else if (n == 8) blk_correct<T, 8>(ul, n, sm + g.ou[l - 1], sm + g.ot[l - 1]);
         else blk_correct<T, 0>(ul, n, sm + g.ou[l - 1], sm + g.ot[l - 1]);
       }
       const int nu = s < 0 ? g.alpha : s < lt ? g.nu1 : g.nu2;
       if (n == 16) blk_gs<T, 16>(ul, rhs, n, nu);
       else if (n == 8) blk_gs<T, 8>(ul, rhs, n, nu);
+      else if (n == 4) blk_gs<T, 4>(ul, rhs, n, nu);
       else blk_gs<T, 0>(ul, rhs, n, nu);
       if (s >= 0 && s < lt)
         blk_descend(ul, rhs, n, sm + g.ou[l - 1], sm + g.orh[l - 1], sm + g.ot[l - 1]);
