@@ -305,7 +305,7 @@ static void build_hier(fmg_plan* P, Hier<T>& H, bool finest_external) {
     if (l < L - 1) {
       H.t[l] = (T*)dalloc(P, sizeof(T) * cnt);
       H.rhs[l] = (T*)dalloc(P, sizeof(T) * cnt);
-      if (!sr && n <= kLatencyEdge) H.rf[l] = (T*)dalloc(P, sizeof(T) * cnt);
+      if (!sr) H.rf[l] = (T*)dalloc(P, sizeof(T) * cnt);  // FAS right-hand side (global levels)
     }
   }
 }
@@ -362,14 +362,14 @@ static bool nonnull(const CoarseArgs<X>& a) {
 }
 
 // profile label of one k_smooth_z instantiation, e.g. "k_smooth_z<load,ns2,ry1>"
-template <int NS, int PRO, int RY, int RES, int PF>
+template <int NS, int PRO, int RY, int RES, int PF, int FAS>
 static const char* zlabel() {
   static const std::string s = std::string("k_smooth_z<") +
                                (PRO == PRO_CORRECT ? "correct" : PRO == PRO_INTERP ? "interp" : "load") +
                                ",ns" +
                                std::to_string(NS) + ",ry" + std::to_string(RY) +
-                               (RES ? ",res" : "") + (PF > 1 ? ",pf" + std::to_string(PF) : "") +
-                               ">";
+                               (RES ? ",res" : "") + (FAS ? ",fas" : "") +
+                               (PF > 1 ? ",pf" + std::to_string(PF) : "") + ">";
   return s.c_str();
 }
 
@@ -482,15 +482,19 @@ struct Exec {
   }
 
   // one temporally blocked launch of NS half-sweeps with prologue PRO; RY
-  // columns per thread; inpl: one workgroup per segment, updated in place
-  template <int NS, int RY, int PRO, int RES = 0, int PF = kPrefetch<NS>>
+  // columns per thread; inpl: one workgroup per segment, updated in place;
+  // FAS: a load pass over two copies on a global level first forms the FAS
+  // right-hand side rhs + L u, into rf, and t = u
+  template <int NS, int RY, int PRO, int RES = 0, int PF = kPrefetch<NS>, int FAS = 0>
   void smooth_z(int l, const T* rhs, Geo gr, const T* c, const T* ct, Geo gc, bool inpl,
                 double* out = nullptr, int outmode = 0, int rmode = -1) {
     constexpr int NT = 1024, NC = NT * RY;
     // two workgroups per CU (at most 64 VGPRs) where the kernel fits them
     // (not the latency variant: its launches are small)
     constexpr int WPE =
-        (PF == 1 && NS <= 2 && !RES && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD))) ? 8 : 4;
+        (PF == 1 && NS <= 2 && !RES && (RY == 1 || (sizeof(T) == 4 && PRO == PRO_LOAD && !FAS)))
+            ? 8
+            : 4;
     const Geo& G = H.geo[l];
     if (PRO != PRO_LOAD && (!c || !ct)) throw hip_error("internal: null coarse increment");
     SmoothArgs<T> a{};
@@ -513,6 +517,12 @@ struct Exec {
     a.uc = RES ? H.u[l - 1] : nullptr;
     a.rc = RES ? H.rhs[l - 1] : nullptr;
     a.gcr = H.geo[l > 0 ? l - 1 : 0];
+    if (FAS && (inpl || G.ghost || nseg(l) != 1 || gr.ghost || gr.n != G.n || !H.rf[l] ||
+                !H.t[l] || rhs == H.rf[l]))
+      throw hip_error("internal: FAS prologue needs a global level over two copies, t and rf");
+    a.fas = FAS;
+    a.rhsw = FAS ? H.rf[l] : nullptr;
+    a.tw = FAS ? H.t[l] : nullptr;
     double h = 1.0 / (double)G.n;
     a.h2 = (T)(h * h);
     int ns = nseg(l);
@@ -613,8 +623,9 @@ struct Exec {
       bytes += 8.0 * outmode * cube(P->N) - sizeof(T) * c_cells(G);
     if (RES)  // uc and rc on the coarse target
       bytes += 2.0 * sizeof(T) * (rmode == 0 ? c_cells(G) / 8.0 : cube(H.geo[l - 1].n));
-    run(zlabel<NS, PRO, RY, RES, PF>(), bytes,
-        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, PF, WPE, RES>,
+    if (FAS) bytes += 2.0 * sizeof(T) * c_cells(G);  // rhs and t written
+    run(zlabel<NS, PRO, RY, RES, PF, FAS>(), bytes,
+        dim3(per * a.nxcd, ns), dim3(NT), k_smooth_z<T, NS, PRO, NT, RY, PF, WPE, RES, FAS>,
         a);
   }
 
@@ -694,10 +705,16 @@ struct Exec {
     // one column per thread for FP64 two-stage passes over two copies (few
     // enough registers for two workgroups per CU), else two
     constexpr int RY2 = sizeof(T) == 8 ? 1 : 2;
-    if (fas && !cols_level(l)) throw hip_error("internal: FAS prologue off the column smoother");
+    if (fas && (inpl || PRO != PRO_LOAD))
+      throw hip_error("internal: FAS prologue off a load pass over two copies");
     if (cols_level(l) && !inpl) {
       if (ns == 2) smooth_cols<2, PRO, 0>(l, rhs, gr, c, ct, gc, fas);
       else smooth_cols<4, PRO, 0>(l, rhs, gr, c, ct, gc, fas);
+    } else if (fas) {  // a large global level
+      if constexpr (PRO == PRO_LOAD) {
+        if (ns == 2) smooth_z<2, RY2, PRO_LOAD, 0, kPrefetch<2>, 1>(l, rhs, gr, c, ct, gc, false);
+        else smooth_z<4, RY2, PRO_LOAD, 0, kPrefetch<4>, 1>(l, rhs, gr, c, ct, gc, false);
+      }
     } else if (!inpl && H.geo[l].n <= kLatencyEdge) {
       if (ns == 2) smooth_z<2, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
       else smooth_z<4, 1, PRO, 0, 2>(l, rhs, gr, c, ct, gc, false);
@@ -714,10 +731,16 @@ struct Exec {
   }
 
   // can the first pre-smoothing pass of level l form its FAS right-hand side
-  // (the column smoother's prologue), so that the restriction into it need
-  // not?
+  // (the column smoother's prologue, or the z march's over two copies on a
+  // larger global level), so that the restriction into it need not?
   bool pass_fas(int l) const {
-    return l > P->Lc && P->fused && P->nu1 > 0 && cols_level(l);
+    if (!(l > P->Lc && P->fused && P->nu1 > 0)) return false;
+    if (cols_level(l)) return true;
+    const Geo& G = H.geo[l];
+    if (G.ghost || nseg(l) != 1) return false;
+    // not when that pass is also the one that restricts (see smooth)
+    const int st = 2 * P->nu1, ns = st >= P->max_stages ? P->max_stages : st;
+    return !(ns == 2 && st == ns && sizeof(T) == 8 && P->zres);
   }
 
   // can level l's segments be smoothed in place, one workgroup each, with

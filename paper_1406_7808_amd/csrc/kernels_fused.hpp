@@ -73,20 +73,22 @@ struct SmoothArgs {
   T* uc;
   T* rc;
   Geo gcr;
-  // FAS prologue (k_smooth_cols, load prologue): rhs holds R res of the level
-  // above; the pass forms rhs = R res + L u (Eq. 4) and uses it, and stores
-  // it over rhs (rhsw) and t = u (tw) on its output cells
+  // FAS prologue (load prologue; k_smooth_cols, and k_smooth_z over two
+  // copies): rhs holds R res of the level above; the pass forms
+  // rhs = R res + L u (Eq. 4) and uses it, and stores it to rhsw and t = u
+  // to tw on its output cells
   int fas;
   T* rhsw;
   T* tw;
 };
 
-template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES>
+template <class T, int NS, int PRO, int NT, int RY, int PF, int WPE, int RES, int FAS = 0>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_smooth_z(SmoothArgs<T> a) {
   constexpr int NC = NT * RY;
   static_assert(PRO == PRO_LOAD || PRO == PRO_CORRECT || PRO == PRO_INTERP, "prologue");
   static_assert(!RES || PRO == PRO_LOAD, "the epilogue follows a load prologue");
+  static_assert(!FAS || (PRO == PRO_LOAD && !RES), "the FAS prologue is a plain load pass's");
   // neighbour exchange: per step parity, the idle class of the NS planes the
   // step's stages update (rank-indexed, see below)
   __shared__ T lds[2][NS][NC / 2];
@@ -102,6 +104,9 @@ k_smooth_z(SmoothArgs<T> a) {
   // (u, or w - t), per step parity
   __shared__ T lci[PRO != PRO_LOAD ? 2 : 1][PRO != PRO_LOAD ? NT : 1];
   __shared__ double lsu[RES ? 2 : 1][RES ? NC : 1], lsr[RES ? 2 : 1][RES ? NC : 1];
+  // FAS prologue: per step parity, the updated class of plane p - 1 before
+  // any half-sweep (the idle class is in the exchange), by rank
+  __shared__ T lfa[FAS ? 2 : 1][FAS ? NC / 2 : 1];
 
   const Geo gu = a.gu;
   const int q = blockIdx.y;
@@ -176,6 +181,8 @@ k_smooth_z(SmoothArgs<T> a) {
   // rhs from LDS)
   constexpr int NU = NS + 2, NF = NS + 1;
   T U[NU][RY], F[NF][RY];
+  // FAS prologue: plane p - 2 as loaded (half-sweeps have changed U[2])
+  T Uo[FAS ? RY : 1];
   T Qu[PF][RY], Qf[PF][RY];  // ring of planes in flight
   // interpolation prologue: this thread's coarse value of a fetched coarse
   // plane in the ring, and the xy-interpolated coarse planes lo and lo + 1 of
@@ -265,6 +272,7 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int j = 0; j < NU; ++j) U[j][r] = 0;
 #pragma unroll
     for (int j = 0; j < NF; ++j) F[j][r] = 0;
+    if (FAS) Uo[r] = 0;
   }
 
   // issue the loads of plane p into a ring slot (raw values, used PF steps
@@ -373,7 +381,45 @@ k_smooth_z(SmoothArgs<T> a) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) ldsr[J][threadIdx.x + NT * r] = U[NS + 1][r];
     }
+    if constexpr (FAS) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (kbh(r) == J) lfa[J][rnk(r)] = U[1][r];
+    }
     __syncthreads();
+    if constexpr (FAS) {
+      // rhs of plane zf = p - 1 becomes R res + L u (FP64; neighbours summed in
+      // the order of the single-cell kernels, out-of-domain ones are the zeros
+      // loaded), on every column the half-sweeps update, before the first
+      // of them (stage 1 of this step) reads it.  Plane p - 1 and the in-plane
+      // neighbours are as loaded; plane p - 2 comes from Uo.
+      const int zf = p - 1;
+      const bool zin = zf >= 0 && zf < n, zout = zf >= oz && zf < oz1;  // uniform
+      const double s2 = (double)n * (double)n;
+      const unsigned nbz = (zf == 0) + (zf == n - 1);
+      const long long pw = (long long)(zf - B.o[2]) * mm;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (zin && (ok[r] & 10u) == 10u) {  // inside C, not a tile edge: neighbours in the tile
+          const T* pl = kbh(r) == J ? lds[J][0] : lfa[J];
+          const int tw2 = txw >> 1, i = rnk(r);
+          const int xn = i - 1 + (int)((ok[r] >> 9) & 1u);
+          double sn = (double)pl[xn];
+          sn += (double)pl[xn + 1];
+          sn += (double)pl[i - tw2];
+          sn += (double)pl[i + tw2];
+          sn += (double)Uo[r];
+          sn += (double)U[0][r];
+          const double nb = (double)(6u + ((ok[r] >> 4) & 7u) + nbz);
+          F[1][r] = (T)((double)F[1][r] + (sn - nb * (double)U[1][r]) * s2);
+          if (zout && (ok[r] & 4u)) {
+            a.rhsw[pw + uo[r]] = F[1][r];
+            a.tw[pw + uo[r]] = U[1][r];
+          }
+        }
+        Uo[r] = U[1][r];
+      }
+    }
     if constexpr (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
 #pragma unroll
       for (int r = 0; r < RY; ++r) U[0][r] = ((vuk >> r) & 1u) ? uq[r] + lci[J][io[r]] : (T)0;

@@ -199,6 +199,39 @@ def test_full_size_global(fourier256):
     assert _rel(u, oracle.fmg(f, 8)) <= TOL
 
 
+def test_full_size_global_four_stage_passes(fourier256):
+    """256^3 global FMG with passes of four half-sweeps: the 128^3 level's
+    single pre-smoothing pass forms its FAS right-hand side (z march over two
+    copies, four stages) and a separate descent restricts."""
+    f = fourier256[0]
+    _say("full global 256 max_stages=4")
+    plan = fmg.Plan(256, 8)
+    plan.set_tuning(max_stages=4)
+    assert _rel(plan.execute(_gpu(f)), oracle.fmg(f, 8)) <= TOL
+    plan.close()
+
+
+def test_full_size_global_one_presmoothing_sweep(fourier256):
+    """256^3 global FMG with one pre-smoothing sweep: the 128^3 level's only
+    pre-smoothing pass is the one that restricts, so its FAS right-hand side
+    comes from the separate column march instead of the pass."""
+    f = fourier256[0]
+    sw = (1, 2, 1)
+    _say("full global 256 sweeps", sw)
+    u = fmg.solve(_gpu(f), 8, sweeps=sw)
+    assert _rel(u, oracle.fmg(f, 8, alpha=sw[2], nu1=sw[0], nu2=sw[1])) <= TOL
+
+
+def test_sr_transition_into_a_large_global_level(fourier256):
+    """SR on the finest level only (256^3, 8^3 segments): the transition level
+    is the 128^3 global level, restricted into by the owner-computes descent;
+    its first pre-smoothing pass forms the FAS right-hand side."""
+    f = fourier256[0]
+    _say("sr 256 K=1")
+    u = fmg.solve(_gpu(f), 8, sr_levels=1, segments=8, buffers=[2])
+    assert _rel(u, oracle.srfmg(f, 8, 1, 8, [2])) <= TOL
+
+
 def test_full_size_sr(fourier256):
     f = fourier256[0]
     _say("full sr 256")
@@ -322,7 +355,8 @@ def test_vcycles_to_tolerance():
 # --- mixed precision --------------------------------------------------------------
 
 @pytest.mark.parametrize("N,L,K,S,J", [(64, 6, 2, 2, [2, 2]), (64, 6, 0, 1, []),
-                                        (128, 7, 3, 4, [2, 4, 6]), (256, 8, 3, 8, [2, 4, 6])])
+                                        (128, 7, 3, 4, [2, 4, 6]), (256, 8, 3, 8, [2, 4, 6]),
+                                        (256, 8, 0, 1, [])])
 def test_fp32_refined_within_discretization_error(N, L, K, S, J):
     _say("fp32r", N, L, K, S, J)
     f, uc, (k, a) = W.fourier(N)
