@@ -192,22 +192,31 @@ def fourier256():
     return f, uc, k, a
 
 
-def test_full_size_global(fourier256):
+@pytest.fixture(scope="module")
+def global256(fourier256):
+    return oracle.fmg(fourier256[0], 8)
+
+
+def test_full_size_global(fourier256, global256):
+    """256^3 global FMG: the 128^3 level's pre-smoothing is one four-stage pass
+    that forms its FAS right-hand side (z march over two copies), then a
+    separate descent restricts."""
     f = fourier256[0]
     _say("full global 256")
     u = fmg.solve(_gpu(f), 8)
-    assert _rel(u, oracle.fmg(f, 8)) <= TOL
+    assert _rel(u, global256) <= TOL
 
 
-def test_full_size_global_four_stage_passes(fourier256):
-    """256^3 global FMG with passes of four half-sweeps: the 128^3 level's
-    single pre-smoothing pass forms its FAS right-hand side (z march over two
-    copies, four stages) and a separate descent restricts."""
+@pytest.mark.parametrize("kw", [dict(max_stages=2), dict(target_blocks=256), dict(tile_x=16)])
+def test_full_size_global_pass_settings(fourier256, global256, kw):
+    """256^3 global FMG under other pass settings: two-stage passes (the 128^3
+    level's FAS prologue in its two-stage variant, followed by a restricting
+    pass), and other z chunkings and tile widths of the FAS pass."""
     f = fourier256[0]
-    _say("full global 256 max_stages=4")
+    _say("full global 256", kw)
     plan = fmg.Plan(256, 8)
-    plan.set_tuning(max_stages=4)
-    assert _rel(plan.execute(_gpu(f)), oracle.fmg(f, 8)) <= TOL
+    plan.set_tuning(**kw)
+    assert _rel(plan.execute(_gpu(f)), global256) <= TOL
     plan.close()
 
 
