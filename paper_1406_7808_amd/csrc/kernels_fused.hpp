@@ -161,7 +161,10 @@ k_smooth_z(SmoothArgs<T> a) {
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
   // (over two copies the residual epilogue's march starts one plane lower, so
   // that the plane below the chunk is final for its residual too)
-  const int p0 = oz - NS - ((RES && !inpl) ? 1 : 0), p1 = zs1 - 1 + NS + 2 * RES;
+  // (the correction starts on an even plane, one warm-up step earlier if
+  // need be, so that the two steps of a pair share a parent plane)
+  const int p00 = oz - NS - ((RES && !inpl) ? 1 : 0);
+  const int p0 = PRO == PRO_CORRECT ? (p00 & ~1) : p00, p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box_d(a.gr, q);
@@ -304,9 +307,13 @@ k_smooth_z(SmoothArgs<T> a) {
     const T c = (T)0.5625 * q0 + ((T)0.1875 * (s1 + s2) + (T)0.0625 * s3);
     return flip ? -c : c;
   };
-  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T& qi, T& qj, unsigned& vu, unsigned& vf) {
+  auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T& qi, T& qj, unsigned& vu, unsigned& vf,
+                   bool ldc) {
     if (PRO == PRO_INTERP) qi = fetch_c(((p - 1) >> 1) + 1);
-    if (PRO == PRO_CORRECT) {  // w and t of the parent plane (no reflection: parents lie inside)
+    // w and t of the parent plane (no reflection: parents lie inside), for
+    // even planes only: fine planes 2P and 2P + 1 share it (ldc is a
+    // compile-time fact of the step that fetches)
+    if (PRO == PRO_CORRECT && ldc) {
       const int P = p >> 1;
       const bool v = tcv && P >= Bc.o[2] && P < Bc.o[2] + a.gc.m;
       const long long ic = v ? (long long)(P - Bc.o[2]) * cmm + tco : 0;
@@ -339,7 +346,7 @@ k_smooth_z(SmoothArgs<T> a) {
     for (int r = 0; r < RY; ++r) clo[r] = chi[r] = cxy(lci[1], r, lo < 0 || lo >= a.gc.n);
   }
 #pragma unroll
-  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qi[k], Qj[k], Vu[k], Vf[k]);
+  for (int k = 0; k < PF; ++k) fetch(p0 + k, Qu[k], Qf[k], Qi[k], Qj[k], Vu[k], Vf[k], (k & 1) == 0);
   // step p0 + j with J = j & 1: the stages update the slots of half J
   auto step = [&](auto Jc, int p) {
     constexpr int J = decltype(Jc)::value, kq = J % PF;
@@ -361,10 +368,17 @@ k_smooth_z(SmoothArgs<T> a) {
       uq[r] = Qu[kq][r];
       F[0][r] = ((Vf[kq] >> r) & 1u) ? Qf[kq][r] : (T)0;
     }
-    if constexpr (PRO != PRO_LOAD) {
-      if ((int)threadIdx.x < ctn) lci[J][threadIdx.x] = PRO == PRO_CORRECT ? Qi[kq] - Qj[kq] : Qi[kq];
+    // the correction stages w - t once per parent plane P (in the pair's even
+    // step, J = 0: p0 is even) in buffer P & 1, which the next write (parent
+    // P + 2) reaches two barriers later
+    const int cbuf = PRO == PRO_CORRECT ? (p >> 1) & 1 : J;
+    if constexpr (PRO == PRO_INTERP) {
+      if ((int)threadIdx.x < ctn) lci[J][threadIdx.x] = Qi[kq];
     }
-    fetch(p + PF, Qu[kq], Qf[kq], Qi[kq], Qj[kq], Vu[kq], Vf[kq]);
+    if constexpr (PRO == PRO_CORRECT && J == 0) {
+      if ((int)threadIdx.x < ctn) lci[cbuf][threadIdx.x] = Qi[kq] - Qj[kq];
+    }
+    fetch(p + PF, Qu[kq], Qf[kq], Qi[kq], Qj[kq], Vu[kq], Vf[kq], ((J + PF) & 1) == 0);
     // NS half-sweeps as a wavefront: stage s applies half-sweep s (colour
     // (s - 1) & 1) to plane p - s.  Its cells read the other colour of that
     // plane as the previous step left it (no stage of this step changes it),
@@ -422,7 +436,7 @@ k_smooth_z(SmoothArgs<T> a) {
     }
     if constexpr (PRO == PRO_CORRECT) {  // u + (w - t) of the parent (Eq. 4's correction, piecewise constant)
 #pragma unroll
-      for (int r = 0; r < RY; ++r) U[0][r] = ((vuk >> r) & 1u) ? uq[r] + lci[J][io[r]] : (T)0;
+      for (int r = 0; r < RY; ++r) U[0][r] = ((vuk >> r) & 1u) ? uq[r] + lci[cbuf][io[r]] : (T)0;
     }
     if constexpr (PRO == PRO_INTERP) {
       // plane p lies between coarse planes lo and lo + 1; lo advances on odd
