@@ -161,10 +161,12 @@ k_smooth_z(SmoothArgs<T> a) {
   static_assert(PF == 1 || PF == 2, "the step pairs cycle the load ring");
   // (over two copies the residual epilogue's march starts one plane lower, so
   // that the plane below the chunk is final for its residual too)
-  // (the correction starts on an even plane, one warm-up step earlier if
-  // need be, so that the two steps of a pair share a parent plane)
+  // (the correction starts on an even plane and the interpolation on an odd
+  // one, one warm-up step earlier if need be, so that the two steps of a pair
+  // share a parent plane, or the pair of coarse planes they lie between)
   const int p00 = oz - NS - ((RES && !inpl) ? 1 : 0);
-  const int p0 = PRO == PRO_CORRECT ? (p00 & ~1) : p00, p1 = zs1 - 1 + NS + 2 * RES;
+  const int p0 = PRO == PRO_CORRECT ? (p00 & ~1) : PRO == PRO_INTERP ? ((p00 - 1) | 1) : p00;
+  const int p1 = zs1 - 1 + NS + 2 * RES;
   const int nsteps = ((p1 - p0 + 1) + 1) / 2 * 2;
 
   const Box Br = seg_box_d(a.gr, q);
@@ -309,7 +311,7 @@ k_smooth_z(SmoothArgs<T> a) {
   };
   auto fetch = [&](int p, T(&qu)[RY], T(&qf)[RY], T& qi, T& qj, unsigned& vu, unsigned& vf,
                    bool ldc) {
-    if (PRO == PRO_INTERP) qi = fetch_c(((p - 1) >> 1) + 1);
+    if (PRO == PRO_INTERP && ldc) qi = fetch_c(((p - 1) >> 1) + 1);  // odd planes only
     // w and t of the parent plane (no reflection: parents lie inside), for
     // even planes only: fine planes 2P and 2P + 1 share it (ldc is a
     // compile-time fact of the step that fetches)
@@ -371,9 +373,11 @@ k_smooth_z(SmoothArgs<T> a) {
     // the correction stages w - t once per parent plane P (in the pair's even
     // step, J = 0: p0 is even) in buffer P & 1, which the next write (parent
     // P + 2) reaches two barriers later
-    const int cbuf = PRO == PRO_CORRECT ? (p >> 1) & 1 : J;
-    if constexpr (PRO == PRO_INTERP) {
-      if ((int)threadIdx.x < ctn) lci[J][threadIdx.x] = Qi[kq];
+    // (the interpolation likewise stages coarse plane lo + 1 once, in the
+    // pair's odd step, J = 0: p0 is odd, in a buffer per pair parity)
+    const int cbuf = PRO == PRO_CORRECT ? (p >> 1) & 1 : PRO == PRO_INTERP ? ((p - p0) >> 1) & 1 : J;
+    if constexpr (PRO == PRO_INTERP && J == 0) {
+      if ((int)threadIdx.x < ctn) lci[cbuf][threadIdx.x] = Qi[kq];
     }
     if constexpr (PRO == PRO_CORRECT && J == 0) {
       if ((int)threadIdx.x < ctn) lci[cbuf][threadIdx.x] = Qi[kq] - Qj[kq];
@@ -440,17 +444,25 @@ k_smooth_z(SmoothArgs<T> a) {
     }
     if constexpr (PRO == PRO_INTERP) {
       // plane p lies between coarse planes lo and lo + 1; lo advances on odd
-      // p, and p takes 3/4 of the nearer one (FMG interpolation: trilinear,
-      // odd reflection at the walls)
-      const int Pn = ((p - 1) >> 1) + 1;
-      const bool flip = Pn < 0 || Pn >= a.gc.n, podd = (p & 1) != 0;
+      // p (J = 0), and p takes 3/4 of the nearer one (FMG interpolation:
+      // trilinear, odd reflection at the walls); the even plane after it
+      // lies between the same two
+      if constexpr (J == 0) {
+        const int Pn = ((p - 1) >> 1) + 1;
+        const bool flip = Pn < 0 || Pn >= a.gc.n;
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const T cn = cxy(lci[J], r, flip);
-        clo[r] = podd ? chi[r] : clo[r];
-        chi[r] = cn;
-        const T v = podd ? (T)0.75 * clo[r] + (T)0.25 * chi[r] : (T)0.75 * chi[r] + (T)0.25 * clo[r];
-        U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
+        for (int r = 0; r < RY; ++r) {
+          clo[r] = chi[r];
+          chi[r] = cxy(lci[cbuf], r, flip);
+          const T v = (T)0.75 * clo[r] + (T)0.25 * chi[r];
+          U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          const T v = (T)0.75 * chi[r] + (T)0.25 * clo[r];
+          U[0][r] = ((vuk >> r) & 1u) ? v : (T)0;
+        }
       }
     }
     // the stages; INNER: all NS planes lie inside C and off the domain's z
