@@ -216,6 +216,9 @@ k_smooth_z(SmoothArgs<T> a) {
     return sl >= NC / 2 ? sl - NC / 2 : sl;
   };
   bool lact[RY];  // the slot's column is updated (inside C, not a tile edge)
+  // 1 / (6 + x and y boundary faces) of the slot's column: the diagonal inverse
+  // of the steps whose planes all lie off the z walls (INNER), without LDS
+  T invr[RY];
   // interpolation and correction prologues: the tile's threads load the
   // coarse columns under the tile, ctx x cty from (cX0, cY0), one each, into
   // LDS.  Per slot: the LDS index of the coarse column (X0, Y0) under its
@@ -262,6 +265,7 @@ k_smooth_z(SmoothArgs<T> a) {
     ok[r] = (st ? 1u : 0u) | (inc ? 2u : 0u) | (outp ? 4u : 0u) | (inner ? 8u : 0u) | (nbxy << 4) |
             (gen ? 128u : 0u) | (own ? 256u : 0u) | ((unsigned)(cx & 1) << 9);
     lact[r] = inc && inner;
+    invr[r] = (T)1 / (T)(6 + (int)nbxy);
     if (PRO != PRO_LOAD) {
       const int nc = a.gc.n, X0 = x >> 1, Y0 = y >> 1;
       const int X1 = (x & 1) ? X0 + 1 : X0 - 1, Y1 = (y & 1) ? Y0 + 1 : Y0 - 1;
@@ -490,7 +494,7 @@ k_smooth_z(SmoothArgs<T> a) {
           // the plane above (just updated by stage s - 1) is added last
           const T sum = (((pl[xn] + pl[xn + 1]) + (pl[i - tw2] + pl[i + tw2])) + U[s + 1][r]) +
                         U[s - 1][r];
-          const T inv = invd[(int)((ok[r] >> 4) & 7u) + nbz];
+          const T inv = INNER ? invr[r] : invd[(int)((ok[r] >> 4) & 7u) + nbz];
           const T nv = (sum - a.h2 * F[s][r]) * inv;
           U[s][r] = lact[r] ? nv : U[s][r];
         }
