@@ -640,8 +640,8 @@ struct Exec {
     constexpr int NT = 1024, HH = NS + RES;
     const Geo& G = H.geo[l];
     const int n = G.n;
-    if (G.ghost || nseg(l) != 1 || (RES && l < 1))
-      throw hip_error("internal: the column smoother takes global levels");
+    if (G.ghost || nseg(l) != 1 || (RES && l < 1) || n < 2)
+      throw hip_error("internal: the column smoother takes global levels of edge 2 and up");
     if (PRO != PRO_LOAD && (!c || (PRO == PRO_CORRECT && !ct)))
       throw hip_error("internal: null coarse increment");
     if (fas && (PRO != PRO_LOAD || !H.t[l] || !H.rf[l]))

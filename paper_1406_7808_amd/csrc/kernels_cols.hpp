@@ -53,7 +53,6 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
                 "chunks of whole coarse planes; the prologues need an even first plane");
   // each column's chunk, plane-major
   __shared__ T ex[Z][NT];
-  __shared__ T invd[8];  // 1 / (6 + nb) for nb = 0..6 boundary faces
   // epilogue: per-column sums over the two fine planes of each coarse plane
   __shared__ double lsu[RES ? ZC / 2 : 1][RES ? NT : 1], lsr[RES ? ZC / 2 : 1][RES ? NT : 1];
 
@@ -96,10 +95,12 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
   const int ir = act ? rk : tw2;
   const int xn = oc + ir - 1 + (cx & 1), yn = oc + ir - tw2, yp = oc + ir + tw2;
   const int nbxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+  // the column's diagonal inverse 1 / (6 + boundary faces) off a z wall and on
+  // one (the levels here have edges of at least 2, so no cell touches both)
+  const T inv0 = (T)1 / (T)(6 + nbxy), inv1 = (T)1 / (T)(7 + nbxy);
   const Box B = seg_box_d(a.gu, 0), Br = seg_box_d(a.gr, 0);
   const long long pu = st ? at(a.gu, B, x, y, 0) : 0, pr = st ? at(a.gr, Br, x, y, 0) : 0;
   const long long mu = (long long)a.gu.m * a.gu.m, mr = (long long)a.gr.m * a.gr.m;
-  if (t < 7) invd[t] = (T)1 / (T)(6 + t);  // read after a barrier
 
   // the chunk: every load issued before the first use.  Lanes with nothing to
   // read fetch element 0; their values are masked.
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(1024) k_smooth_cols(SmoothArgs<T> a) {
     const T below = j > 0 ? U[j > 0 ? j - 1 : 0] : (T)0;
     const T above = j < Z - 1 ? U[j < Z - 1 ? j + 1 : 0] : (T)0;
     const T sum = (((pl[xn] + pl[xn + 1]) + (pl[yn] + pl[yp])) + below) + above;
-    const T inv = invd[nbxy + (z == 0) + (z == n - 1)];
+    const T inv = (z == 0 || z == n - 1) ? inv1 : inv0;
     const T nv = (sum - a.h2 * F[j]) * inv;
     const bool upd = act && j > 0 && j < Z - 1 && z >= 0 && z < n;
     U[j] = upd ? nv : U[j];
